@@ -1,0 +1,180 @@
+/*
+ * sar.h -- C ABI of the MI355X (gfx950) near-field MIMO-SAR image-formation
+ * library for irregular (multi-planar, multistatic) scanning geometries.
+ *
+ * Method: J. W. Smith and M. Torlak, "Efficient 3-D Near-Field MIMO-SAR
+ * Imaging for Irregular Scanning Geometries", IEEE Access (2022).
+ * Equation numbers below count the paper's displayed equations in order
+ * ((1) far-field criterion ... (17) spatial resolution).
+ *
+ * Pipeline of one scan (Sec. III, Fig. 3):
+ *   a0  virtual elements x' = (x_T + x_R)/2, y' likewise, d = x_R - x_T,
+ *       d^z = z_l - Z_0 (Eqs. (3)-(4)); residual path
+ *       beta = 2 sign(Z_0 - z_c) d^z + (d_x^2 + d_y^2) / (4 |z_c - Z_0|)
+ *       (Eqs. (7), (12) written in the array frame);
+ *   a1  compensation s_hat = s exp(+j k beta), k = 2 pi f / c (Eq. (11));
+ *   a2  Kaiser-Bessel gridding of the irregular (x', y') samples onto an
+ *       oversampled uniform grid (type-1 NUFFT spreading, the FT_2D of
+ *       Eq. (16) evaluated with a NUFFT as in Sec. III);
+ *   a3  2-D FFT, deapodisation and crop to the image's (k_x, k_y) modes:
+ *       S(p,q,f) ~ sum_n s_hat_n(f) exp(-j[k_x,p (x'_n - x_c) + k_y,q (y'_n - y_c)]),
+ *       k_x,p = 2 pi p / (nx dx), p = -nx/2 .. nx/2-1, x_c = x0 + (nx/2) dx;
+ *   a4  filter k_z exp(-j k_z Z_0) / P(f), P = 1, k_z^2 = 4k^2 - k_x^2 - k_y^2,
+ *       evanescent modes dropped (Eqs. (14)-(15));
+ *   a5  Stolt map onto uniform k_z and the z transform, evaluated as a 1-D
+ *       type-1 NUFFT per (k_x, k_y) column of
+ *       Z(p,q,z_w) = sum_f F(p,q,f) exp(+j k_z z_w), z_w = z0 + w dz;
+ *   a6  inverse 2-D transform to the image (rest of IFT_3D, Eq. (16)):
+ *       o(u,v,w) = sum_{p,q} Z(p,q,w) exp(+j[k_x,p (x_u - x_c) + k_y,q (y_v - y_c)]),
+ *       unnormalised.
+ *
+ * Conventions
+ *   - Units: metres, hertz.  c = 299 792 458 m/s.
+ *   - Layouts (all row-major, last index fastest):
+ *       positions  double [n_pos][3]                      (x, y, z of the device origin per shot)
+ *       echo       [n_pos][n_tx*n_rx][n_freq]  pair = t*n_rx + r
+ *                  SAR_ECHO_C64: float2 (re, im);  SAR_ECHO_F16X2: two IEEE halves (re, im),
+ *                  value = half * echo_scale
+ *       spectrum   float2 [ny][nx][n_freq]   mode index j = p + nx/2 (centred)
+ *       image      float2 [nx][ny][nz]       voxel (u,v,w) at (x0+u dx, y0+v dy, z0+w dz)
+ *   - Device pointers ("d_") are HIP device memory on the plan's device and are
+ *     owned by the caller.  Host arrays passed to sar_plan_create are copied;
+ *     the caller may free them on return.
+ *   - Every call returns a status; nothing aborts or throws across the ABI.
+ *     On failure sar_last_error() describes the cause (thread-local string,
+ *     valid until the next call on the same thread).
+ *   - Compute calls are asynchronous and ordered on the given HIP stream
+ *     (NULL = the null stream); they do not allocate and do not synchronise.
+ */
+#ifndef SAR_H_
+#define SAR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sar_plan_s* sar_plan;
+typedef void* sar_stream_t; /* a hipStream_t */
+
+typedef enum {
+  SAR_OK = 0,
+  SAR_ERR_INVALID = 1,     /* bad argument or descriptor */
+  SAR_ERR_NOMEM = 2,       /* device allocation failed */
+  SAR_ERR_DEVICE = 3,      /* HIP runtime / launch error */
+  SAR_ERR_BUSY = 4,        /* resource has work in flight */
+  SAR_ERR_NOT_FOUND = 5,   /* unknown handle or ticket */
+  SAR_ERR_UNSUPPORTED = 6  /* valid request the library does not implement */
+} sar_status;
+
+typedef enum { SAR_ECHO_C64 = 0, SAR_ECHO_F16X2 = 1 } sar_echo_type;
+
+/* flags */
+#define SAR_NO_COMPENSATION 0x1u /* beta = 0: plain RMA on raw multi-planar data (Sec. III ablation) */
+
+/* Plan descriptor: array geometry, frequency sweep and image grid.
+ * Constraints (SAR_ERR_INVALID otherwise):
+ *   n_tx, n_rx >= 1; n_freq >= 1, freq_hz finite, strictly increasing, > 0;
+ *   nx, ny, nz even powers of two with 8 <= nx, ny <= 4096 and 2 <= nz <= 2048;
+ *   dx, dy, dz > 0; z_focus != z_ref and the image volume in front of the
+ *   projection plane (z0 > z_ref, z_focus > z_ref);
+ *   max_pos >= 0; tol in (0, 0.1] (target relative error of each NUFFT;
+ *   0 selects 1e-4); upsample 0 (automatic = 2) or >= 2 (the lateral grid is
+ *   the next power of two at or above upsample * n); kernel_width 0 (from tol)
+ *   or 3..8 taps. */
+typedef struct {
+  int32_t n_tx;
+  int32_t n_rx;
+  const double* tx_xy; /* [n_tx][2] Tx offsets from the device origin; z offset 0 */
+  const double* rx_xy; /* [n_rx][2] Rx offsets from the device origin; z offset 0 */
+  int32_t n_freq;
+  const double* freq_hz; /* [n_freq] stepped frequencies */
+  double z_ref;          /* Z_0: plane the samples are projected on (Eqs. (4), (10)) */
+  double z_focus;        /* z_c: scene reference depth for beta's multistatic term */
+  int32_t nx, ny, nz;
+  double x0, y0, z0; /* first voxel centre */
+  double dx, dy, dz; /* voxel pitch */
+  int64_t max_pos;   /* largest n_pos a workspace from this plan must serve */
+  int32_t echo_type; /* sar_echo_type */
+  double tol;
+  double upsample;
+  int32_t kernel_width;
+  uint32_t flags;
+} sar_plan_desc;
+
+/* What a plan chose (read-only). */
+typedef struct {
+  int32_t mx, my;        /* oversampled lateral grid (cells) */
+  int32_t width;         /* lateral Kaiser-Bessel kernel width (taps) */
+  double kb_beta;        /* its shape parameter */
+  int32_t mz;            /* oversampled Stolt grid (cells) */
+  int32_t width_z;       /* Stolt kernel width (taps) */
+  double es_beta_z;      /* its shape parameter */
+  int32_t n_pair;        /* n_tx * n_rx */
+  int32_t n_stages;      /* entries returned by sar_plan_stage_times */
+  size_t workspace_bytes_max; /* workspace for n_pos = max_pos */
+} sar_plan_info;
+
+/* Create a plan on HIP device `device`: validates the descriptor, chooses the
+ * NUFFT parameters, and uploads its tables (wavenumbers, deapodisation,
+ * twiddles, pair offsets) to the device, where they stay until
+ * sar_plan_destroy.  Geometry: Sec. II-B; sweep: Sec. II-C; grid: Sec. III.
+ * Errors: SAR_ERR_INVALID (descriptor), SAR_ERR_NOMEM, SAR_ERR_DEVICE. */
+sar_status sar_plan_create(const sar_plan_desc* desc, int device, sar_plan* out);
+
+/* Release the plan's device tables.  The caller must ensure no work that uses
+ * the plan is still queued.  NULL is accepted. */
+sar_status sar_plan_destroy(sar_plan plan);
+
+/* Bytes of device workspace sar_reconstruct / sar_spectrum /
+ * sar_image_from_spectrum need for a scan of n_pos shots (0 <= n_pos <= max_pos). */
+sar_status sar_plan_workspace_bytes(sar_plan plan, int64_t n_pos, size_t* bytes);
+
+sar_status sar_plan_get_info(sar_plan plan, sar_plan_info* info);
+
+/* Steps a0-a6: image of one scan.
+ *   d_pos       device double [n_pos][3]
+ *   n_pos       shots in this scan, 0 <= n_pos <= max_pos (0 gives a zero image)
+ *   d_echo      device echo [n_pos][n_pair][n_freq] of the plan's echo type
+ *   echo_scale  multiplies every echo value (use 1 for SAR_ECHO_C64)
+ *   d_image     device float2 [nx][ny][nz], written
+ *   d_workspace device scratch of sar_plan_workspace_bytes(plan, n_pos) bytes,
+ *               256-byte aligned; contents undefined afterwards
+ *   stream      HIP stream the work is queued on
+ * Asynchronous; errors reported here are argument errors and launch errors. */
+sar_status sar_reconstruct(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,
+                           float echo_scale, void* d_image, void* d_workspace, sar_stream_t stream);
+
+/* Steps a0-a3 only: the compensated spatial spectrum S, written to
+ * d_spectrum (device float2 [ny][nx][n_freq], centred mode order). */
+sar_status sar_spectrum(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,
+                        float echo_scale, void* d_spectrum, void* d_workspace, sar_stream_t stream);
+
+/* Steps a4-a6 only: image of a given spectrum (layout as sar_spectrum's
+ * output).  d_workspace needs sar_plan_workspace_bytes(plan, 0) bytes. */
+sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* d_image, void* d_workspace,
+                                   sar_stream_t stream);
+
+/* Per-stage timing with HIP events recorded on the call's stream around each
+ * kernel group (stage order: 0 geometry+sort, 1 gridding, 2 FFT along x,
+ * 3 FFT along y, 4 Stolt, 5 inverse FFT along y, 6 inverse FFT along x).
+ * enable != 0 starts recording (and clears earlier records);
+ * sar_plan_stage_times waits for the recorded events, returns the summed
+ * milliseconds per stage over all recorded calls and their count, and clears
+ * the records.  ms must hold sar_plan_info.n_stages doubles. */
+sar_status sar_plan_set_timing(sar_plan plan, int enable);
+sar_status sar_plan_stage_times(sar_plan plan, double* ms, int32_t n, int64_t* n_calls);
+
+/* Thread-local description of the last failure on this thread. */
+const char* sar_last_error(void);
+
+/* Library version string. */
+const char* sar_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAR_H_ */

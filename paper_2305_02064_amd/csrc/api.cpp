@@ -1,0 +1,314 @@
+// C ABI entry points (include/sar.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "sar_internal.hpp"
+
+namespace sar {
+
+sar_status validate_desc(const sar_plan_desc* d);
+sar_status build_plan(const sar_plan_desc* d, int device, Plan& p);
+void free_plan(Plan& p);
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+sar_status fail(sar_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+sar_status check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SAR_OK;
+  return fail(SAR_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+namespace {
+
+// switches to the plan's device for the duration of a call
+struct DeviceGuard {
+  int old = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) == hipSuccess && old != dev) changed = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(old);
+  }
+};
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+struct Timer {
+  Plan& p;
+  hipStream_t s;
+  hipEvent_t ev[kNumStages + 1] = {};
+  bool on;
+  Timer(Plan& plan, hipStream_t stream, bool enable) : p(plan), s(stream), on(enable) {
+    if (!on) return;
+    for (auto& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        return;
+      }
+  }
+  void mark(int i) {
+    if (on) (void)hipEventRecord(ev[i], s);
+  }
+  void commit() {
+    if (!on) return;
+    for (auto& e : ev) p.events.push_back(e);
+    p.timed_calls += 1;
+  }
+};
+
+sar_status run_front(Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
+                     float2* spec_out, const Workspace& ws, hipStream_t stream, Timer& tm) {
+  sar_status st;
+  tm.mark(0);
+  if ((st = launch_geometry_sort(p, d_pos, n_pos, ws, stream)) != SAR_OK) return st;
+  tm.mark(1);
+  if ((st = launch_gridding(p, n_pos, d_echo, echo_scale, ws, ws.region_a, stream)) != SAR_OK) return st;
+  tm.mark(2);
+  FftLines fx{};
+  fx.in = ws.region_a;
+  fx.out = ws.region_b;
+  fx.L = p.mx;
+  fx.n_outer = p.my;
+  fx.B = p.nf;
+  fx.s_in_o = (int64_t)p.mx * p.nf;
+  fx.s_in_l = p.nf;
+  fx.s_out_o = (int64_t)p.nx * p.nf;
+  fx.s_out_k = p.nf;
+  fx.n_out = p.nx;
+  fx.centred = 1;
+  fx.sign = -1;
+  fx.scale = p.d_deapx;
+  fx.tw = p.d_tw_mx;
+  if ((st = launch_fft_lines(fx, stream)) != SAR_OK) return st;
+  tm.mark(3);
+  FftLines fy{};
+  fy.in = ws.region_b;
+  fy.out = spec_out;
+  fy.L = p.my;
+  fy.n_outer = 1;
+  fy.B = (int64_t)p.nx * p.nf;
+  fy.s_in_o = 0;
+  fy.s_in_l = (int64_t)p.nx * p.nf;
+  fy.s_out_o = 0;
+  fy.s_out_k = (int64_t)p.nx * p.nf;
+  fy.n_out = p.ny;
+  fy.centred = 1;
+  fy.sign = -1;
+  fy.scale = p.d_deapy;
+  fy.tw = p.d_tw_my;
+  if ((st = launch_fft_lines(fy, stream)) != SAR_OK) return st;
+  tm.mark(4);
+  return SAR_OK;
+}
+
+sar_status run_back(Plan& p, const float2* spec, void* d_image, const Workspace& ws, hipStream_t stream,
+                    Timer& tm, int first_mark) {
+  sar_status st;
+  tm.mark(first_mark);
+  if ((st = launch_stolt(p, spec, ws.region_b, stream)) != SAR_OK) return st;
+  tm.mark(first_mark + 1);
+  FftLines gy{};
+  gy.in = ws.region_b;  // [ny][nx][nz]
+  gy.out = ws.region_a; // [ny(v)][nx][nz]
+  gy.L = p.ny;
+  gy.n_outer = 1;
+  gy.B = (int64_t)p.nx * p.nz;
+  gy.s_in_o = 0;
+  gy.s_in_l = (int64_t)p.nx * p.nz;
+  gy.s_out_o = 0;
+  gy.s_out_k = (int64_t)p.nx * p.nz;
+  gy.n_out = p.ny;
+  gy.centred = 0;
+  gy.sign = +1;
+  gy.scale = p.d_signy;
+  gy.tw = p.d_tw_ny;
+  if ((st = launch_fft_lines(gy, stream)) != SAR_OK) return st;
+  tm.mark(first_mark + 2);
+  FftLines gx{};
+  gx.in = ws.region_a;  // [v][P][w]
+  gx.out = (float2*)d_image;  // [u][v][w]
+  gx.L = p.nx;
+  gx.n_outer = p.ny;
+  gx.B = p.nz;
+  gx.s_in_o = (int64_t)p.nx * p.nz;
+  gx.s_in_l = p.nz;
+  gx.s_out_o = p.nz;
+  gx.s_out_k = (int64_t)p.ny * p.nz;
+  gx.n_out = p.nx;
+  gx.centred = 0;
+  gx.sign = +1;
+  gx.scale = p.d_signx;
+  gx.tw = p.d_tw_nx;
+  if ((st = launch_fft_lines(gx, stream)) != SAR_OK) return st;
+  tm.mark(first_mark + 3);
+  return SAR_OK;
+}
+
+sar_status check_call(sar_plan plan, int64_t n_pos, const void* d_pos, const void* d_echo, const void* d_out,
+                      const void* d_ws) {
+  if (!plan) return fail(SAR_ERR_INVALID, "plan is NULL");
+  const Plan& p = plan->p;
+  if (n_pos < 0 || n_pos > p.max_pos) return fail(SAR_ERR_INVALID, "n_pos outside [0, max_pos]");
+  if (n_pos > 0 && (!d_pos || !d_echo)) return fail(SAR_ERR_INVALID, "positions or echo pointer is NULL");
+  if (!d_out) return fail(SAR_ERR_INVALID, "output pointer is NULL");
+  if (!d_ws) return fail(SAR_ERR_INVALID, "workspace pointer is NULL");
+  if (!aligned256(d_ws)) return fail(SAR_ERR_INVALID, "workspace must be 256-byte aligned");
+  return SAR_OK;
+}
+
+}  // namespace
+}  // namespace sar
+
+using namespace sar;
+
+extern "C" {
+
+const char* sar_last_error(void) { return g_last_error.c_str(); }
+
+const char* sar_version(void) { return "sar-mi355x 0.1 (gfx950)"; }
+
+sar_status sar_plan_create(const sar_plan_desc* desc, int device, sar_plan* out) {
+  if (!out) return fail(SAR_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  try {
+    // validate before any HIP call, so descriptor errors never touch a device
+    sar_status vs = validate_desc(desc);
+    if (vs != SAR_OK) return vs;
+    sar_plan h = new (std::nothrow) sar_plan_s();
+    if (!h) return fail(SAR_ERR_NOMEM, "host allocation failed");
+    int old = -1;
+    (void)hipGetDevice(&old);
+    sar_status st = build_plan(desc, device, h->p);
+    if (old >= 0 && old != device) (void)hipSetDevice(old);
+    if (st != SAR_OK) {
+      free_plan(h->p);
+      delete h;
+      return st;
+    }
+    *out = h;
+    return SAR_OK;
+  } catch (...) {
+    return fail(SAR_ERR_INVALID, "exception during plan creation");
+  }
+}
+
+sar_status sar_plan_destroy(sar_plan plan) {
+  if (!plan) return SAR_OK;
+  DeviceGuard g(plan->p.device);
+  free_plan(plan->p);
+  delete plan;
+  return SAR_OK;
+}
+
+sar_status sar_plan_workspace_bytes(sar_plan plan, int64_t n_pos, size_t* bytes) {
+  if (!plan || !bytes) return fail(SAR_ERR_INVALID, "plan or bytes is NULL");
+  if (n_pos < 0 || n_pos > plan->p.max_pos) return fail(SAR_ERR_INVALID, "n_pos outside [0, max_pos]");
+  *bytes = workspace_bytes(plan->p, n_pos, nullptr, nullptr);
+  return SAR_OK;
+}
+
+sar_status sar_plan_get_info(sar_plan plan, sar_plan_info* info) {
+  if (!plan || !info) return fail(SAR_ERR_INVALID, "plan or info is NULL");
+  const Plan& p = plan->p;
+  std::memset(info, 0, sizeof(*info));
+  info->mx = p.mx;
+  info->my = p.my;
+  info->width = p.w;
+  info->kb_beta = p.kb_beta;
+  info->mz = p.mz;
+  info->width_z = p.wz;
+  info->es_beta_z = p.es_beta;
+  info->n_pair = p.n_pair;
+  info->n_stages = kNumStages;
+  info->workspace_bytes_max = workspace_bytes(p, p.max_pos, nullptr, nullptr);
+  return SAR_OK;
+}
+
+sar_status sar_reconstruct(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,
+                           float echo_scale, void* d_image, void* d_workspace, sar_stream_t stream) {
+  sar_status st = check_call(plan, n_pos, d_pos, d_echo, d_image, d_workspace);
+  if (st != SAR_OK) return st;
+  Plan& p = plan->p;
+  DeviceGuard g(p.device);
+  Workspace ws;
+  workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
+  hipStream_t s = (hipStream_t)stream;
+  Timer tm(p, s, p.timing);
+  if ((st = run_front(p, d_pos, n_pos, d_echo, echo_scale, ws.region_a, ws, s, tm)) != SAR_OK) return st;
+  if ((st = run_back(p, ws.region_a, d_image, ws, s, tm, 4)) != SAR_OK) return st;
+  tm.commit();
+  return SAR_OK;
+}
+
+sar_status sar_spectrum(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
+                        void* d_spectrum, void* d_workspace, sar_stream_t stream) {
+  sar_status st = check_call(plan, n_pos, d_pos, d_echo, d_spectrum, d_workspace);
+  if (st != SAR_OK) return st;
+  Plan& p = plan->p;
+  DeviceGuard g(p.device);
+  Workspace ws;
+  workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
+  Timer tm(p, (hipStream_t)stream, false);
+  return run_front(p, d_pos, n_pos, d_echo, echo_scale, (float2*)d_spectrum, ws, (hipStream_t)stream, tm);
+}
+
+sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* d_image, void* d_workspace,
+                                   sar_stream_t stream) {
+  sar_status st = check_call(plan, 0, nullptr, nullptr, d_image, d_workspace);
+  if (st != SAR_OK) return st;
+  if (!d_spectrum) return fail(SAR_ERR_INVALID, "spectrum pointer is NULL");
+  Plan& p = plan->p;
+  DeviceGuard g(p.device);
+  Workspace ws;
+  workspace_bytes(p, 0, &ws, (char*)d_workspace);
+  Timer tm(p, (hipStream_t)stream, false);
+  return run_back(p, (const float2*)d_spectrum, d_image, ws, (hipStream_t)stream, tm, 4);
+}
+
+sar_status sar_plan_set_timing(sar_plan plan, int enable) {
+  if (!plan) return fail(SAR_ERR_INVALID, "plan is NULL");
+  DeviceGuard g(plan->p.device);
+  for (hipEvent_t ev : plan->p.events) (void)hipEventDestroy(ev);
+  plan->p.events.clear();
+  plan->p.timed_calls = 0;
+  plan->p.timing = enable != 0;
+  return SAR_OK;
+}
+
+sar_status sar_plan_stage_times(sar_plan plan, double* ms, int32_t n, int64_t* n_calls) {
+  if (!plan || !ms || n < kNumStages) return fail(SAR_ERR_INVALID, "need a plan and kNumStages outputs");
+  Plan& p = plan->p;
+  DeviceGuard g(p.device);
+  for (int i = 0; i < n; ++i) ms[i] = 0.0;
+  const size_t per = kNumStages + 1;
+  sar_status st = SAR_OK;
+  for (size_t c = 0; c + per <= p.events.size(); c += per) {
+    if (hipEventSynchronize(p.events[c + kNumStages]) != hipSuccess) {
+      st = fail(SAR_ERR_DEVICE, "event wait failed");
+      break;
+    }
+    for (int s = 0; s < kNumStages; ++s) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, p.events[c + s], p.events[c + s + 1]) == hipSuccess) ms[s] += t;
+    }
+  }
+  if (n_calls) *n_calls = p.timed_calls;
+  for (hipEvent_t ev : p.events) (void)hipEventDestroy(ev);
+  p.events.clear();
+  p.timed_calls = 0;
+  return st;
+}
+
+}  // extern "C"

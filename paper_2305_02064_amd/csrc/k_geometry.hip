@@ -1,0 +1,288 @@
+// Step a0: virtual elements, residual path and sorted gridding records.
+//
+// Every Tx/Rx pair of every shot becomes a virtual element at the pair's
+// midpoint projected onto the plane Z_0 (Eqs. (3)-(4)); its residual path
+// beta (Eqs. (7), (12)) is kept for the phase compensation applied in the
+// gridding kernel.  The elements are then counting-sorted by the oversampled
+// grid cell of their first kernel tap so that the gridding kernel can walk
+// every sample whose support touches a tile as a handful of contiguous runs.
+// Within a cell the order is by source index, so results are reproducible.
+
+#include "device_common.hpp"
+#include "sar_internal.hpp"
+
+namespace sar {
+namespace {
+
+struct GeoArgs {
+  const double* pos;     // [n_pos][3]
+  const double* pair;    // [n_pair][4]: midpoint offset x, y; multistatic beta term; unused
+  int64_t n_v;
+  int n_pair;
+  double xc, yc;         // lateral centre of the image grid
+  double gsx, gsy;       // metres -> oversampled cells
+  int mx, my;
+  double z_ref;
+  double beta_sign;      // 2 sign(Z_0 - z_c), or 0 without compensation
+  double kb_beta, inv_i0_beta;
+};
+
+__device__ __forceinline__ double bessel_i0(double x) {
+  // power series of the modified Bessel function of the first kind, order 0
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 80; ++k) {
+    term *= q / ((double)k * (double)k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+// Kaiser-Bessel kernel of width W (cells), normalised to 1 at the centre.
+__device__ __forceinline__ double kb_weight(double d, int W, double beta, double inv_i0_beta) {
+  const double z = 2.0 * d / (double)W;
+  const double r = 1.0 - z * z;
+  if (r <= 0.0) return 0.0;
+  return bessel_i0(beta * sqrt(r)) * inv_i0_beta;
+}
+
+// grid coordinate in [0, m) and first-tap cell for a kernel of width W
+__device__ __forceinline__ void grid_coord(double rel, double scale, int m, int W, double& g, int& c0) {
+  double t = rel * scale;
+  t -= floor(t / (double)m) * (double)m;
+  if (t >= (double)m) t -= (double)m;
+  g = t;
+  c0 = (int)floor(t - 0.5 * W) + 1;
+}
+
+__device__ __forceinline__ int wrap(int c, int m) { return c < 0 ? c + m : (c >= m ? c - m : c); }
+
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+template <int W>
+__global__ void k_keys(GeoArgs a, int32_t* __restrict__ key, int32_t* __restrict__ rank,
+                       int32_t* __restrict__ count) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= a.n_v) return;
+  const int64_t m = n / a.n_pair;
+  const int l = (int)(n - m * a.n_pair);
+  const double xv = a.pos[3 * m + 0] + a.pair[4 * l + 0];
+  const double yv = a.pos[3 * m + 1] + a.pair[4 * l + 1];
+  double gx, gy;
+  int cx, cy;
+  grid_coord(xv - a.xc, a.gsx, a.mx, W, gx, cx);
+  grid_coord(yv - a.yc, a.gsy, a.my, W, gy, cy);
+  const int k = wrap(cy, a.my) * a.mx + wrap(cx, a.mx);
+  key[n] = k;
+  rank[n] = atomicAdd(&count[k], 1);
+}
+
+// ---- exclusive scan of the per-cell counts (three passes) -----------------
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanChunk = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* smem_waves, int& total) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) smem_waves[wave] = incl;
+  __syncthreads();
+  if (wave == 0) {
+    const int nw = blockDim.x >> 6;
+    int w = lane < nw ? smem_waves[lane] : 0;
+    int wi = w;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(wi, off, 64);
+      if (lane >= off) wi += t;
+    }
+    if (lane < nw) smem_waves[lane] = wi - w;  // exclusive wave offsets
+    if (lane == nw - 1) smem_waves[64] = wi;   // block total
+  }
+  __syncthreads();
+  total = smem_waves[64];
+  return incl - v + smem_waves[wave];
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(int32_t* __restrict__ data, int64_t n,
+                                                            int32_t* __restrict__ bsum) {
+  __shared__ int smem[65];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? data[base + i] : 0;
+    s += v[i];
+  }
+  int total;
+  int run = block_exclusive_scan(s, smem, total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) data[base + i] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int32_t* __restrict__ bsum, int nb,
+                                                           int32_t* __restrict__ total_out) {
+  __shared__ int smem[65];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nb; c0 += kScanChunk) {
+    const int base = c0 + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      v[i] = (base + i < nb) ? bsum[base + i] : 0;
+      s += v[i];
+    }
+    int total;
+    int run = block_exclusive_scan(s, smem, total) + carry;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      if (base + i < nb) bsum[base + i] = run;
+      run += v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total_out = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* __restrict__ data, int64_t n,
+                                                          const int32_t* __restrict__ bsum) {
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+  const int off = bsum[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) data[base + i] += off;
+}
+
+__global__ void k_scatter(int64_t n_v, const int32_t* __restrict__ key, const int32_t* __restrict__ rank,
+                          const int32_t* __restrict__ start, int32_t* __restrict__ order) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= n_v) return;
+  order[start[key[n]] + rank[n]] = (int32_t)n;
+}
+
+// One thread per cell: order the cell's samples by source index, then write
+// their records (geometry recomputed in float64 from the shot position).
+template <int W>
+__global__ void k_records(GeoArgs a, const int32_t* __restrict__ start, int32_t* __restrict__ order,
+                          SampleRec<W>* __restrict__ rec) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)a.mx * a.my) return;
+  const int s0 = start[c], s1 = start[c + 1];
+  for (int i = s0 + 1; i < s1; ++i) {
+    const int v = order[i];
+    int j = i - 1;
+    while (j >= s0 && order[j] > v) {
+      order[j + 1] = order[j];
+      --j;
+    }
+    order[j + 1] = v;
+  }
+  for (int s = s0; s < s1; ++s) {
+    const int64_t n = order[s];
+    const int64_t m = n / a.n_pair;
+    const int l = (int)(n - m * a.n_pair);
+    const double xv = a.pos[3 * m + 0] + a.pair[4 * l + 0];
+    const double yv = a.pos[3 * m + 1] + a.pair[4 * l + 1];
+    const double dzv = a.pos[3 * m + 2] - a.z_ref;
+    double gx, gy;
+    int cx, cy;
+    grid_coord(xv - a.xc, a.gsx, a.mx, W, gx, cx);
+    grid_coord(yv - a.yc, a.gsy, a.my, W, gy, cy);
+    SampleRec<W> r;
+    r.src = (int32_t)n;
+    r.cx = (int16_t)wrap(cx, a.mx);
+    r.cy = (int16_t)wrap(cy, a.my);
+    r.beta = a.beta_sign * dzv + a.pair[4 * l + 2];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      r.wx[j] = (float)kb_weight((double)(cx + j) - gx, W, a.kb_beta, a.inv_i0_beta);
+      r.wy[j] = (float)kb_weight((double)(cy + j) - gy, W, a.kb_beta, a.inv_i0_beta);
+    }
+    rec[s] = r;
+  }
+}
+
+template <int W>
+sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, const Workspace& ws,
+                           hipStream_t stream) {
+  const int64_t n_v = n_pos * p.n_pair;
+  const int64_t ncell = (int64_t)p.mx * p.my;
+  GeoArgs a;
+  a.pos = d_pos;
+  a.pair = p.d_pair;
+  a.n_v = n_v;
+  a.n_pair = p.n_pair;
+  a.xc = p.xc;
+  a.yc = p.yc;
+  a.gsx = (double)p.mx / ((double)p.nx * p.dx);
+  a.gsy = (double)p.my / ((double)p.ny * p.dy);
+  a.mx = p.mx;
+  a.my = p.my;
+  a.z_ref = p.z_ref;
+  a.beta_sign = p.beta_sign;
+  a.kb_beta = p.kb_beta;
+  // 1 / I0(beta) evaluated with the same series on the host
+  {
+    const double q = 0.25 * p.kb_beta * p.kb_beta;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 80; ++k) {
+      term *= q / ((double)k * (double)k);
+      sum += term;
+      if (term < 1e-17 * sum) break;
+    }
+    a.inv_i0_beta = 1.0 / sum;
+  }
+  const int tb = 256;
+  k_zero_i32<<<(unsigned)((ncell + 1 + tb - 1) / tb), tb, 0, stream>>>(ws.cell_start, ncell + 1);
+  if (n_v > 0)
+    k_keys<W><<<(unsigned)((n_v + tb - 1) / tb), tb, 0, stream>>>(a, ws.key, ws.rank, ws.cell_start);
+  const int nb = (int)((ncell + kScanChunk - 1) / kScanChunk);
+  int32_t* bsum = ws.cell_start + ncell + 1;
+  k_scan_local<<<nb, kScanThreads, 0, stream>>>(ws.cell_start, ncell, bsum);
+  k_scan_sums<<<1, kScanThreads, 0, stream>>>(bsum, nb, ws.cell_start + ncell);
+  k_scan_add<<<nb, kScanThreads, 0, stream>>>(ws.cell_start, ncell, bsum);
+  if (n_v > 0) {
+    k_scatter<<<(unsigned)((n_v + tb - 1) / tb), tb, 0, stream>>>(n_v, ws.key, ws.rank, ws.cell_start,
+                                                                  ws.order);
+    k_records<W><<<(unsigned)((ncell + tb - 1) / tb), tb, 0, stream>>>(a, ws.cell_start, ws.order,
+                                                                       (SampleRec<W>*)ws.rec);
+  }
+  return check_hip(hipGetLastError(), "geometry/sort launch");
+}
+
+}  // namespace
+
+sar_status launch_geometry_sort(const Plan& p, const double* d_pos, int64_t n_pos, const Workspace& ws,
+                                hipStream_t stream) {
+  switch (p.w) {
+    case 3: return geometry_sort_w<3>(p, d_pos, n_pos, ws, stream);
+    case 4: return geometry_sort_w<4>(p, d_pos, n_pos, ws, stream);
+    case 5: return geometry_sort_w<5>(p, d_pos, n_pos, ws, stream);
+    case 6: return geometry_sort_w<6>(p, d_pos, n_pos, ws, stream);
+    case 7: return geometry_sort_w<7>(p, d_pos, n_pos, ws, stream);
+    case 8: return geometry_sort_w<8>(p, d_pos, n_pos, ws, stream);
+    default: return fail(SAR_ERR_UNSUPPORTED, "kernel width not compiled");
+  }
+}
+
+}  // namespace sar

@@ -1,0 +1,332 @@
+// Plan construction: descriptor validation, NUFFT parameters, float64 tables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sar_internal.hpp"
+
+namespace sar {
+
+namespace {
+
+constexpr double kC0 = 299792458.0;
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int next_pow2(int64_t v) {
+  int r = 1;
+  while (r < v) r <<= 1;
+  return r;
+}
+
+double bessel_i0_host(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 200; ++k) {
+    term *= q / ((double)k * (double)k);
+    sum += term;
+    if (term < 1e-17 * sum) break;
+  }
+  return sum;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on the three-term
+// recurrence of the Legendre polynomials).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      // p1 = P_n(z), p0 = P_{n-1}(z)
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Fourier transform of a symmetric kernel supported on [-W/2, W/2]:
+//   phi_hat(p) = int phi(x) cos(2 pi p x / M) dx,
+// by Gauss-Legendre quadrature after x = (W/2) sin(theta), which removes the
+// square-root behaviour of the kernels at the support edge.
+template <typename K>
+std::vector<double> kernel_ft(const K& phi, int W, int M, int n_modes) {
+  std::vector<double> gx, gw;
+  gauss_legendre(256, gx, gw);
+  std::vector<double> out(n_modes);
+  for (int j = 0; j < n_modes; ++j) {
+    const double p = (double)(j - n_modes / 2);
+    double s = 0.0;
+    for (size_t i = 0; i < gx.size(); ++i) {
+      const double th = 0.5 * M_PI * gx[i];
+      const double x = 0.5 * W * std::sin(th);
+      s += gw[i] * phi(x) * std::cos(2.0 * M_PI * p * x / M) * 0.5 * W * std::cos(th);
+    }
+    out[j] = s * 0.5 * M_PI;
+  }
+  return out;
+}
+
+template <typename T>
+sar_status upload(T** dst, const std::vector<T>& v) {
+  if (v.empty()) {
+    *dst = nullptr;
+    return SAR_OK;
+  }
+  hipError_t e = hipMalloc((void**)dst, v.size() * sizeof(T));
+  if (e != hipSuccess) return fail(SAR_ERR_NOMEM, "hipMalloc for plan tables failed");
+  e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return check_hip(e, "plan table upload");
+}
+
+std::vector<float2> twiddles(int n, int sign) {
+  std::vector<float2> t(n);
+  for (int i = 0; i < n; ++i) {
+    const double a = sign * 2.0 * M_PI * (double)i / (double)n;
+    t[i] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  return t;
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+// rough relative error of a width-W kernel at oversampling sigma
+double nufft_error_estimate(int W, double sigma) { return std::exp(-M_PI * W * std::sqrt(1.0 - 1.0 / sigma)); }
+
+sar_status validate_desc(const sar_plan_desc* d) {
+  if (!d) return fail(SAR_ERR_INVALID, "descriptor is NULL");
+  if (d->n_tx < 1 || d->n_rx < 1 || !d->tx_xy || !d->rx_xy) return fail(SAR_ERR_INVALID, "array layout missing");
+  if ((int64_t)d->n_tx * d->n_rx > 4096) return fail(SAR_ERR_INVALID, "too many Tx/Rx pairs");
+  for (int i = 0; i < 2 * d->n_tx; ++i)
+    if (!finite(d->tx_xy[i])) return fail(SAR_ERR_INVALID, "non-finite Tx offset");
+  for (int i = 0; i < 2 * d->n_rx; ++i)
+    if (!finite(d->rx_xy[i])) return fail(SAR_ERR_INVALID, "non-finite Rx offset");
+  if (d->n_freq < 1 || !d->freq_hz) return fail(SAR_ERR_INVALID, "frequency sweep missing");
+  for (int i = 0; i < d->n_freq; ++i) {
+    if (!finite(d->freq_hz[i]) || d->freq_hz[i] <= 0) return fail(SAR_ERR_INVALID, "frequency must be finite and > 0");
+    if (i > 0 && !(d->freq_hz[i] > d->freq_hz[i - 1]))
+      return fail(SAR_ERR_INVALID, "frequencies must be strictly increasing");
+  }
+  auto okn = [](int v, int lo, int hi) { return v >= lo && v <= hi && is_pow2(v); };
+  if (!okn(d->nx, 8, 2048) || !okn(d->ny, 8, 2048))
+    return fail(SAR_ERR_INVALID, "nx, ny must be powers of two in [8, 2048]");
+  if (!okn(d->nz, 2, 1024)) return fail(SAR_ERR_INVALID, "nz must be a power of two in [2, 1024]");
+  const double g[] = {d->x0, d->y0, d->z0, d->dx, d->dy, d->dz, d->z_ref, d->z_focus};
+  for (double v : g)
+    if (!finite(v)) return fail(SAR_ERR_INVALID, "non-finite grid or plane");
+  if (!(d->dx > 0 && d->dy > 0 && d->dz > 0)) return fail(SAR_ERR_INVALID, "voxel pitch must be > 0");
+  if (!(d->z_focus > d->z_ref)) return fail(SAR_ERR_INVALID, "z_focus must lie in front of z_ref (z_focus > z_ref)");
+  if (!(d->z0 > d->z_ref)) return fail(SAR_ERR_INVALID, "image volume must lie in front of z_ref (z0 > z_ref)");
+  if (d->max_pos < 0) return fail(SAR_ERR_INVALID, "max_pos must be >= 0");
+  if (d->max_pos * (int64_t)d->n_tx * d->n_rx > 0x7fffffffLL)
+    return fail(SAR_ERR_INVALID, "max_pos * n_pair exceeds 2^31 - 1");
+  if (d->echo_type != SAR_ECHO_C64 && d->echo_type != SAR_ECHO_F16X2)
+    return fail(SAR_ERR_INVALID, "unknown echo type");
+  if (!(d->tol == 0 || (d->tol > 0 && d->tol <= 0.1))) return fail(SAR_ERR_INVALID, "tol must be 0 or in (0, 0.1]");
+  if (!(d->upsample == 0 || (d->upsample >= 2 && d->upsample <= 4)))
+    return fail(SAR_ERR_UNSUPPORTED, "upsample must be 0 or in [2, 4]");
+  if (!(d->kernel_width == 0 || (d->kernel_width >= 3 && d->kernel_width <= kMaxWidth)))
+    return fail(SAR_ERR_INVALID, "kernel_width must be 0 or 3..8");
+  if (d->flags & ~SAR_NO_COMPENSATION) return fail(SAR_ERR_INVALID, "unknown flag bits");
+  return SAR_OK;
+}
+
+sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
+  sar_status st = validate_desc(d);
+  if (st != SAR_OK) return st;
+  p.device = device;
+  p.n_tx = d->n_tx;
+  p.n_rx = d->n_rx;
+  p.n_pair = d->n_tx * d->n_rx;
+  p.nf = d->n_freq;
+  p.tx_xy.assign(d->tx_xy, d->tx_xy + 2 * d->n_tx);
+  p.rx_xy.assign(d->rx_xy, d->rx_xy + 2 * d->n_rx);
+  p.freq.assign(d->freq_hz, d->freq_hz + d->n_freq);
+  p.z_ref = d->z_ref;
+  p.z_focus = d->z_focus;
+  p.nx = d->nx;
+  p.ny = d->ny;
+  p.nz = d->nz;
+  p.x0 = d->x0;
+  p.y0 = d->y0;
+  p.z0 = d->z0;
+  p.dx = d->dx;
+  p.dy = d->dy;
+  p.dz = d->dz;
+  p.max_pos = d->max_pos;
+  p.echo_type = d->echo_type;
+  p.tol = d->tol > 0 ? d->tol : 1e-3;
+  p.flags = d->flags;
+  p.xc = p.x0 + (p.nx / 2) * p.dx;
+  p.yc = p.y0 + (p.ny / 2) * p.dy;
+
+  // lateral NUFFT: power-of-two oversampled grid, Kaiser-Bessel kernel
+  const double up = d->upsample > 0 ? d->upsample : 2.0;
+  p.mx = next_pow2((int64_t)std::ceil(up * p.nx - 1e-9));
+  p.my = next_pow2((int64_t)std::ceil(up * p.ny - 1e-9));
+  const double sigma = std::min((double)p.mx / p.nx, (double)p.my / p.ny);
+  if (d->kernel_width > 0) {
+    p.w = d->kernel_width;
+  } else {
+    p.w = kMaxWidth;
+    for (int w = 3; w <= kMaxWidth; ++w)
+      if (nufft_error_estimate(w, sigma) <= p.tol) {
+        p.w = w;
+        break;
+      }
+  }
+  // shape parameter of Beatty, Nishimura and Pauly (2005)
+  {
+    const double a = (p.w / sigma) * (sigma - 0.5);
+    p.kb_beta = M_PI * std::sqrt(std::max(a * a - 0.8, 1e-6));
+  }
+  // Stolt NUFFT: oversampled LDS grid, exponential-of-semicircle kernel
+  p.mz = std::max(64, next_pow2(2 * (int64_t)p.nz));
+  p.wz = p.tol < 1e-5 ? 8 : 6;
+  p.es_beta = 2.30 * p.wz;
+
+  if (p.flags & SAR_NO_COMPENSATION) {
+    p.beta_sign = 0.0;
+    p.inv4rc = 0.0;
+  } else {
+    p.beta_sign = 2.0 * (p.z_ref > p.z_focus ? 1.0 : -1.0);
+    p.inv4rc = 1.0 / (4.0 * std::fabs(p.z_focus - p.z_ref));
+  }
+
+  // ---- tables ----
+  std::vector<double> fcc(p.nf), kk(p.nf);
+  for (int i = 0; i < p.nf; ++i) {
+    fcc[i] = p.freq[i] / kC0;
+    kk[i] = 2.0 * M_PI * p.freq[i] / kC0;
+  }
+  std::vector<double> pair(4 * (size_t)p.n_pair);
+  for (int t = 0; t < p.n_tx; ++t)
+    for (int r = 0; r < p.n_rx; ++r) {
+      const int l = t * p.n_rx + r;
+      const double ox = 0.5 * (p.tx_xy[2 * t] + p.rx_xy[2 * r]);
+      const double oy = 0.5 * (p.tx_xy[2 * t + 1] + p.rx_xy[2 * r + 1]);
+      const double sx = p.rx_xy[2 * r] - p.tx_xy[2 * t];
+      const double sy = p.rx_xy[2 * r + 1] - p.tx_xy[2 * t + 1];
+      pair[4 * l + 0] = ox;
+      pair[4 * l + 1] = oy;
+      pair[4 * l + 2] = (sx * sx + sy * sy) * p.inv4rc;
+      pair[4 * l + 3] = 0.0;
+    }
+  const double kb_norm = 1.0 / bessel_i0_host(p.kb_beta);
+  const int W = p.w;
+  const double kbb = p.kb_beta;
+  auto kb = [W, kbb, kb_norm](double x) {
+    const double z = 2.0 * x / W;
+    const double r = 1.0 - z * z;
+    return r > 0 ? bessel_i0_host(kbb * std::sqrt(r)) * kb_norm : 0.0;
+  };
+  const int WZ = p.wz;
+  const double esb = p.es_beta;
+  auto es = [WZ, esb](double x) {
+    const double z = 2.0 * x / WZ;
+    const double r = 1.0 - z * z;
+    return r > 0 ? std::exp(esb * (std::sqrt(r) - 1.0)) : 0.0;
+  };
+  const std::vector<double> fx = kernel_ft(kb, W, p.mx, p.nx);
+  const std::vector<double> fy = kernel_ft(kb, W, p.my, p.ny);
+  const std::vector<double> fz = kernel_ft(es, WZ, p.mz, p.nz);
+  std::vector<float> deapx(p.nx), deapy(p.ny), deapz(p.nz), signx(p.nx), signy(p.ny);
+  for (int i = 0; i < p.nx; ++i) {
+    deapx[i] = (float)(1.0 / fx[i]);
+    signx[i] = ((i + p.nx / 2) & 1) ? -1.f : 1.f;
+  }
+  for (int i = 0; i < p.ny; ++i) {
+    deapy[i] = (float)(1.0 / fy[i]);
+    signy[i] = ((i + p.ny / 2) & 1) ? -1.f : 1.f;
+  }
+  for (int i = 0; i < p.nz; ++i) deapz[i] = (float)(1.0 / fz[i]);
+
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return check_hip(e, "hipSetDevice");
+  if ((st = upload(&p.d_fcc, fcc)) != SAR_OK) return st;
+  if ((st = upload(&p.d_k, kk)) != SAR_OK) return st;
+  if ((st = upload(&p.d_pair, pair)) != SAR_OK) return st;
+  if ((st = upload(&p.d_deapx, deapx)) != SAR_OK) return st;
+  if ((st = upload(&p.d_deapy, deapy)) != SAR_OK) return st;
+  if ((st = upload(&p.d_deapz, deapz)) != SAR_OK) return st;
+  if ((st = upload(&p.d_signx, signx)) != SAR_OK) return st;
+  if ((st = upload(&p.d_signy, signy)) != SAR_OK) return st;
+  if ((st = upload(&p.d_tw_mx, twiddles(p.mx, -1))) != SAR_OK) return st;
+  if ((st = upload(&p.d_tw_my, twiddles(p.my, -1))) != SAR_OK) return st;
+  if ((st = upload(&p.d_tw_nx, twiddles(p.nx, +1))) != SAR_OK) return st;
+  if ((st = upload(&p.d_tw_ny, twiddles(p.ny, +1))) != SAR_OK) return st;
+  if ((st = upload(&p.d_tw_mz, twiddles(p.mz, +1))) != SAR_OK) return st;
+  return SAR_OK;
+}
+
+void free_plan(Plan& p) {
+  void* ptrs[] = {p.d_fcc, p.d_k, p.d_pair, p.d_deapx, p.d_deapy, p.d_deapz, p.d_signx,
+                  p.d_signy, p.d_tw_mx, p.d_tw_my, p.d_tw_nx, p.d_tw_ny, p.d_tw_mz};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  for (hipEvent_t ev : p.events) (void)hipEventDestroy(ev);
+  p.events.clear();
+}
+
+size_t rec_bytes(int W) {
+  switch (W) {
+    case 3: return sizeof(SampleRec<3>);
+    case 4: return sizeof(SampleRec<4>);
+    case 5: return sizeof(SampleRec<5>);
+    case 6: return sizeof(SampleRec<6>);
+    case 7: return sizeof(SampleRec<7>);
+    default: return sizeof(SampleRec<8>);
+  }
+}
+
+// Workspace layout; with base != nullptr also fills the pointers.
+size_t workspace_bytes(const Plan& p, int64_t n_pos, Workspace* ws, char* base) {
+  auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const int64_t n_v = n_pos * p.n_pair;
+  const int64_t ncell = (int64_t)p.mx * p.my;
+  const int64_t nscan = (ncell + 4095) / 4096;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = al(off + bytes);
+    return o;
+  };
+  const size_t o_cell = take((size_t)(ncell + 1 + nscan) * 4);
+  const size_t o_key = take((size_t)n_v * 4);
+  const size_t o_rank = take((size_t)n_v * 4);
+  const size_t o_order = take((size_t)n_v * 4);
+  const size_t o_rec = take((size_t)n_v * rec_bytes(p.w));
+  const int64_t a_elems = std::max((int64_t)p.mx * p.my * p.nf, (int64_t)p.nx * p.ny * p.nz);
+  const int64_t b_elems = std::max((int64_t)p.my * p.nx * p.nf, (int64_t)p.nx * p.ny * p.nz);
+  const size_t o_a = take((size_t)a_elems * sizeof(float2));
+  const size_t o_b = take((size_t)b_elems * sizeof(float2));
+  if (ws && base) {
+    ws->cell_start = (int32_t*)(base + o_cell);
+    ws->key = (int32_t*)(base + o_key);
+    ws->rank = (int32_t*)(base + o_rank);
+    ws->order = (int32_t*)(base + o_order);
+    ws->rec = (void*)(base + o_rec);
+    ws->region_a = (float2*)(base + o_a);
+    ws->region_b = (float2*)(base + o_b);
+  }
+  return off;
+}
+
+}  // namespace sar

@@ -1,0 +1,114 @@
+// Host-side plan structure and kernel launchers of the image-formation library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sar.h"
+
+namespace sar {
+
+constexpr int kNumStages = 7;
+constexpr int kTile = 8;        // gridding tile edge (cells)
+constexpr int kMaxWidth = 8;    // largest lateral kernel width
+
+// Geometry of one virtual-sample record in the sorted list consumed by the
+// gridding kernel: source row of the echo, base cell (first tap), residual
+// path and the separable kernel weights of its W taps along x and y.
+template <int W>
+struct alignas(16) SampleRec {
+  int32_t src;     // shot * n_pair + pair
+  int16_t cx, cy;  // base cell (first tap), 0 <= cx < mx, 0 <= cy < my
+  double beta;     // residual path (m)
+  float wx[W];
+  float wy[W];
+};
+
+struct Plan {
+  int device = 0;
+  // descriptor copy
+  int n_tx = 0, n_rx = 0, n_pair = 0, nf = 0;
+  std::vector<double> tx_xy, rx_xy, freq;
+  double z_ref = 0, z_focus = 0;
+  int nx = 0, ny = 0, nz = 0;
+  double x0 = 0, y0 = 0, z0 = 0, dx = 0, dy = 0, dz = 0;
+  int64_t max_pos = 0;
+  int echo_type = SAR_ECHO_C64;
+  double tol = 1e-4;
+  uint32_t flags = 0;
+  // derived
+  double xc = 0, yc = 0;     // lateral centre of the image grid
+  int mx = 0, my = 0, w = 0; // oversampled lateral grid and KB width
+  double kb_beta = 0;
+  int mz = 0, wz = 0;        // Stolt grid and ES width
+  double es_beta = 0;
+  double beta_sign = 0, inv4rc = 0;  // beta = beta_sign * dz + (dx^2 + dy^2) * inv4rc
+  // device tables
+  double* d_fcc = nullptr;     // f_i / c (cycles per metre) [nf]
+  double* d_k = nullptr;       // k_i = 2 pi f_i / c [nf]
+  double* d_pair = nullptr;    // [n_pair][4]: midpoint offset (x, y), separation (x, y)
+  float* d_deapx = nullptr;    // 1 / phi_hat_x(p), p = -nx/2 .. [nx]
+  float* d_deapy = nullptr;    // [ny]
+  float* d_deapz = nullptr;    // 1 / phi_hat_z(m), m = -nz/2 .. [nz]
+  float* d_signx = nullptr;    // (-1)^(u + nx/2) [nx]
+  float* d_signy = nullptr;    // (-1)^(v + ny/2) [ny]
+  float2* d_tw_mx = nullptr;   // exp(-j 2 pi i / mx) [mx]
+  float2* d_tw_my = nullptr;
+  float2* d_tw_nx = nullptr;   // exp(+j 2 pi i / nx) [nx]
+  float2* d_tw_ny = nullptr;
+  float2* d_tw_mz = nullptr;   // exp(+j 2 pi i / mz) [mz]
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // kNumStages + 1 per recorded call
+  int64_t timed_calls = 0;
+};
+
+struct Workspace {
+  int32_t* cell_start = nullptr;  // [mx*my + 1]
+  int32_t* key = nullptr;         // [n_v]
+  int32_t* rank = nullptr;        // [n_v]
+  int32_t* order = nullptr;       // [n_v]
+  void* rec = nullptr;            // [n_v] SampleRec<w>
+  float2* region_a = nullptr;     // oversampled grid / spectrum / first inverse pass
+  float2* region_b = nullptr;     // x-transformed grid / z profiles
+};
+
+size_t workspace_bytes(const Plan& p, int64_t n_pos, Workspace* ws, char* base);
+
+// error helpers
+void set_error(const std::string& msg);
+sar_status fail(sar_status st, const std::string& msg);
+sar_status check_hip(hipError_t e, const char* what);
+
+// stage launchers (all asynchronous on `stream`)
+sar_status launch_geometry_sort(const Plan& p, const double* d_pos, int64_t n_pos, const Workspace& ws,
+                                hipStream_t stream);
+sar_status launch_gridding(const Plan& p, int64_t n_pos, const void* d_echo, float echo_scale,
+                           const Workspace& ws, float2* grid, hipStream_t stream);
+// batched 1-D FFT along a strided axis with a contiguous batch dimension:
+// in(o, l, b) = in[o*s_in_o + l*s_in_l + b], l < L, b < B;
+// out(o, P, b) = scale[P] * X(o, k(P), b) at out[o*s_out_o + P*s_out_k + b],
+// where k(P) = P (natural) or (P - n_out/2) mod L (centred crop).
+struct FftLines {
+  const float2* in;
+  float2* out;
+  int L;
+  int n_outer;
+  int64_t B;
+  int64_t s_in_o, s_in_l, s_out_o, s_out_k;
+  int n_out;
+  int centred;
+  int sign;  // -1 forward, +1 inverse
+  const float* scale;
+  const float2* tw;  // exp(sign j 2 pi i / L), i < L
+};
+sar_status launch_fft_lines(const FftLines& a, hipStream_t stream);
+sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, hipStream_t stream);
+
+}  // namespace sar
+
+struct sar_plan_s {
+  sar::Plan p;
+};

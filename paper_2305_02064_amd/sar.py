@@ -1,0 +1,260 @@
+"""Thin Python binding of libsar (include/sar.h).
+
+Argument marshalling only: every step of the image formation runs in the HIP
+kernels of libsar.so.  PyTorch provides device memory and streams; tensors are
+passed to the library as raw device pointers.  Importing this module loads the
+in-tree libsar.so and fails loudly when it is missing (there is no fallback).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch  # noqa: F401  (loads the HIP runtime the library shares with torch)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsar.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "sar.h")
+
+SAR_OK = 0
+SAR_ERR_INVALID = 1
+SAR_ERR_NOMEM = 2
+SAR_ERR_DEVICE = 3
+SAR_ERR_BUSY = 4
+SAR_ERR_NOT_FOUND = 5
+SAR_ERR_UNSUPPORTED = 6
+STATUS_NAMES = {0: "SAR_OK", 1: "SAR_ERR_INVALID", 2: "SAR_ERR_NOMEM", 3: "SAR_ERR_DEVICE", 4: "SAR_ERR_BUSY",
+                5: "SAR_ERR_NOT_FOUND", 6: "SAR_ERR_UNSUPPORTED"}
+
+SAR_ECHO_C64 = 0
+SAR_ECHO_F16X2 = 1
+SAR_NO_COMPENSATION = 0x1
+
+STAGES = ("geometry+sort", "gridding", "fft_x", "fft_y", "stolt", "ifft_y", "ifft_x")
+
+
+class SarError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class sar_plan_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_tx", ctypes.c_int32), ("n_rx", ctypes.c_int32),
+        ("tx_xy", ctypes.POINTER(ctypes.c_double)), ("rx_xy", ctypes.POINTER(ctypes.c_double)),
+        ("n_freq", ctypes.c_int32), ("freq_hz", ctypes.POINTER(ctypes.c_double)),
+        ("z_ref", ctypes.c_double), ("z_focus", ctypes.c_double),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("z0", ctypes.c_double),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+        ("max_pos", ctypes.c_int64),
+        ("echo_type", ctypes.c_int32),
+        ("tol", ctypes.c_double), ("upsample", ctypes.c_double),
+        ("kernel_width", ctypes.c_int32), ("flags", ctypes.c_uint32),
+    ]
+
+
+class sar_plan_info(ctypes.Structure):
+    _fields_ = [
+        ("mx", ctypes.c_int32), ("my", ctypes.c_int32), ("width", ctypes.c_int32),
+        ("kb_beta", ctypes.c_double),
+        ("mz", ctypes.c_int32), ("width_z", ctypes.c_int32),
+        ("es_beta_z", ctypes.c_double),
+        ("n_pair", ctypes.c_int32), ("n_stages", ctypes.c_int32),
+        ("workspace_bytes_max", ctypes.c_size_t),
+    ]
+
+
+_lib = None
+
+
+def library():
+    """Load libsar.so (once).  Raises ImportError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsar.so not found at {LIB_PATH}; build it with "
+                          f"`python -m paper_2305_02064_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    sig = {
+        "sar_plan_create": ([ctypes.POINTER(sar_plan_desc), ctypes.c_int, ctypes.POINTER(vp)], i32),
+        "sar_plan_destroy": ([vp], i32),
+        "sar_plan_workspace_bytes": ([vp, i64, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "sar_plan_get_info": ([vp, ctypes.POINTER(sar_plan_info)], i32),
+        "sar_reconstruct": ([vp, vp, i64, vp, f32, vp, vp, vp], i32),
+        "sar_spectrum": ([vp, vp, i64, vp, f32, vp, vp, vp], i32),
+        "sar_image_from_spectrum": ([vp, vp, vp, vp, vp], i32),
+        "sar_plan_set_timing": ([vp, ctypes.c_int], i32),
+        "sar_plan_stage_times": ([vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i64)], i32),
+        "sar_last_error": ([], ctypes.c_char_p),
+        "sar_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def header_symbols():
+    """Names of the functions include/sar.h declares."""
+    with open(HEADER_PATH) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\**(sar_\w+)\s*\(", txt, flags=re.M)))
+
+
+def _check(status):
+    if status != SAR_OK:
+        raise SarError(status, library().sar_last_error().decode())
+
+
+def sar_last_error():
+    return library().sar_last_error().decode()
+
+
+def sar_version():
+    return library().sar_version().decode()
+
+
+def _dptr(t, name, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def sar_plan_create(tx_xy, rx_xy, freq_hz, nx, ny, nz, x0, y0, z0, dx, dy, dz, z_ref, z_focus, max_pos,
+                    echo_type=SAR_ECHO_C64, tol=0.0, upsample=0.0, kernel_width=0, flags=0, device=0):
+    """Create a plan (see sar_plan_create in include/sar.h); returns an opaque handle."""
+    import numpy as np
+    lib = library()
+    tx = np.ascontiguousarray(tx_xy, dtype=np.float64).reshape(-1, 2)
+    rx = np.ascontiguousarray(rx_xy, dtype=np.float64).reshape(-1, 2)
+    fr = np.ascontiguousarray(freq_hz, dtype=np.float64).ravel()
+    dp = ctypes.POINTER(ctypes.c_double)
+    d = sar_plan_desc(
+        n_tx=len(tx), n_rx=len(rx), tx_xy=tx.ctypes.data_as(dp), rx_xy=rx.ctypes.data_as(dp),
+        n_freq=len(fr), freq_hz=fr.ctypes.data_as(dp), z_ref=z_ref, z_focus=z_focus,
+        nx=nx, ny=ny, nz=nz, x0=x0, y0=y0, z0=z0, dx=dx, dy=dy, dz=dz, max_pos=max_pos,
+        echo_type=echo_type, tol=tol, upsample=upsample, kernel_width=kernel_width, flags=flags)
+    h = ctypes.c_void_p()
+    _check(lib.sar_plan_create(ctypes.byref(d), int(device), ctypes.byref(h)))
+    return h
+
+
+def sar_plan_destroy(plan):
+    _check(library().sar_plan_destroy(plan))
+
+
+def sar_plan_workspace_bytes(plan, n_pos):
+    b = ctypes.c_size_t()
+    _check(library().sar_plan_workspace_bytes(plan, int(n_pos), ctypes.byref(b)))
+    return int(b.value)
+
+
+def sar_plan_get_info(plan):
+    info = sar_plan_info()
+    _check(library().sar_plan_get_info(plan, ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in sar_plan_info._fields_}
+
+
+def sar_reconstruct(plan, pos, n_pos, echo, echo_scale, image, workspace, stream=None):
+    _check(library().sar_reconstruct(plan, _dptr(pos, "pos", torch.float64), int(n_pos), _dptr(echo, "echo"),
+                                     float(echo_scale), _dptr(image, "image", torch.complex64),
+                                     _dptr(workspace, "workspace"), _stream(stream)))
+
+
+def sar_spectrum(plan, pos, n_pos, echo, echo_scale, spectrum, workspace, stream=None):
+    _check(library().sar_spectrum(plan, _dptr(pos, "pos", torch.float64), int(n_pos), _dptr(echo, "echo"),
+                                  float(echo_scale), _dptr(spectrum, "spectrum", torch.complex64),
+                                  _dptr(workspace, "workspace"), _stream(stream)))
+
+
+def sar_image_from_spectrum(plan, spectrum, image, workspace, stream=None):
+    _check(library().sar_image_from_spectrum(plan, _dptr(spectrum, "spectrum", torch.complex64),
+                                             _dptr(image, "image", torch.complex64),
+                                             _dptr(workspace, "workspace"), _stream(stream)))
+
+
+def sar_plan_set_timing(plan, enable):
+    _check(library().sar_plan_set_timing(plan, 1 if enable else 0))
+
+
+def sar_plan_stage_times(plan):
+    """Summed per-stage milliseconds over the recorded calls, and their count."""
+    ms = (ctypes.c_double * len(STAGES))()
+    n = ctypes.c_int64()
+    _check(library().sar_plan_stage_times(plan, ms, len(STAGES), ctypes.byref(n)))
+    return dict(zip(STAGES, list(ms))), int(n.value)
+
+
+class Plan:
+    """Owns a plan handle plus a device workspace sized for max_pos shots."""
+
+    def __init__(self, tx_xy, rx_xy, freq_hz, grid, max_pos, device=0, **kw):
+        self.grid = grid
+        self.device = torch.device("cuda", device)
+        self.n_pair = len(tx_xy) * len(rx_xy)
+        self.n_freq = len(freq_hz)
+        self.handle = sar_plan_create(tx_xy, rx_xy, freq_hz, grid.nx, grid.ny, grid.nz, grid.x0, grid.y0,
+                                      grid.z0, grid.dx, grid.dy, grid.dz, grid.z_ref, grid.z_focus, max_pos,
+                                      device=device, **kw)
+        self.info = sar_plan_get_info(self.handle)
+        self.max_pos = max_pos
+        nbytes = max(self.info["workspace_bytes_max"], 256)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws = self.workspace[off:off + nbytes]
+
+    def new_image(self):
+        g = self.grid
+        return torch.empty((g.nx, g.ny, g.nz), dtype=torch.complex64, device=self.device)
+
+    def new_spectrum(self):
+        g = self.grid
+        return torch.empty((g.ny, g.nx, self.n_freq), dtype=torch.complex64, device=self.device)
+
+    def reconstruct(self, pos, echo, image=None, echo_scale=1.0, stream=None):
+        image = self.new_image() if image is None else image
+        sar_reconstruct(self.handle, pos, pos.shape[0], echo, echo_scale, image, self.ws, stream)
+        return image
+
+    def spectrum(self, pos, echo, spec=None, echo_scale=1.0, stream=None):
+        spec = self.new_spectrum() if spec is None else spec
+        sar_spectrum(self.handle, pos, pos.shape[0], echo, echo_scale, spec, self.ws, stream)
+        return spec
+
+    def image_from_spectrum(self, spec, image=None, stream=None):
+        image = self.new_image() if image is None else image
+        sar_image_from_spectrum(self.handle, spec, image, self.ws, stream)
+        return image
+
+    def close(self):
+        if self.handle is not None:
+            sar_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad descriptors before touching a device."""
+
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2305_02064_amd", "libsar.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libsar.so not built")
+
+
+def _sar():
+    from paper_2305_02064_amd import sar
+    return sar
+
+
+def test_exports_every_declared_symbol():
+    sar = _sar()
+    names = sar.header_symbols()
+    assert {"sar_plan_create", "sar_reconstruct", "sar_spectrum", "sar_image_from_spectrum",
+            "sar_plan_destroy", "sar_last_error"} <= set(names)
+    lib = ctypes.CDLL(sar.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_error_string():
+    sar = _sar()
+    assert "gfx950" in sar.sar_version()
+    assert isinstance(sar.sar_last_error(), str)
+
+
+def _desc_kwargs(**over):
+    from sarsynth import awr1443_layout, sweep
+    tx, rx = awr1443_layout()
+    kw = dict(tx_xy=tx, rx_xy=rx, freq_hz=sweep(16), nx=32, ny=32, nz=16, x0=-0.1, y0=-0.1, z0=0.2,
+              dx=0.2 / 32, dy=0.2 / 32, dz=0.0125, z_ref=0.0, z_focus=0.3, max_pos=100)
+    kw.update(over)
+    return kw
+
+
+@pytest.mark.parametrize("bad,needle", [
+    (dict(nx=30), "powers of two"),
+    (dict(ny=4), "powers of two"),
+    (dict(nz=3), "nz"),
+    (dict(freq_hz=np.array([78e9, 77e9])), "increasing"),
+    (dict(freq_hz=np.array([77e9, np.nan])), "finite"),
+    (dict(dx=0.0), "pitch"),
+    (dict(z_focus=-0.3), "z_focus"),
+    (dict(z0=-0.1), "image volume"),
+    (dict(max_pos=-1), "max_pos"),
+    (dict(max_pos=2 ** 30), "2^31"),
+    (dict(kernel_width=9), "kernel_width"),
+    (dict(tol=0.5), "tol"),
+    (dict(flags=0x80), "flag"),
+    (dict(echo_type=7), "echo type"),
+])
+def test_descriptor_validation(bad, needle):
+    sar = _sar()
+    with pytest.raises(sar.SarError) as ei:
+        sar.sar_plan_create(**_desc_kwargs(**bad))
+    assert ei.value.status == sar.SAR_ERR_INVALID
+    assert needle in str(ei.value)
+
+
+def test_upsample_out_of_range_is_unsupported():
+    sar = _sar()
+    with pytest.raises(sar.SarError) as ei:
+        sar.sar_plan_create(**_desc_kwargs(upsample=1.5))
+    assert ei.value.status == sar.SAR_ERR_UNSUPPORTED
+
+
+def test_null_arguments():
+    sar = _sar()
+    lib = sar.library()
+    b = ctypes.c_size_t()
+    assert lib.sar_plan_workspace_bytes(None, 0, ctypes.byref(b)) == sar.SAR_ERR_INVALID
+    assert lib.sar_reconstruct(None, None, 0, None, 1.0, None, None, None) == sar.SAR_ERR_INVALID
+    assert lib.sar_plan_create(None, 0, None) == sar.SAR_ERR_INVALID
+    assert lib.sar_plan_destroy(None) == sar.SAR_OK
