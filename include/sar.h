@@ -76,14 +76,18 @@ typedef enum { SAR_ECHO_C64 = 0, SAR_ECHO_F16X2 = 1 } sar_echo_type;
 
 /* Plan descriptor: array geometry, frequency sweep and image grid.
  * Constraints (SAR_ERR_INVALID otherwise):
- *   n_tx, n_rx >= 1; n_freq >= 1, freq_hz finite, strictly increasing, > 0;
- *   nx, ny, nz even powers of two with 8 <= nx, ny <= 4096 and 2 <= nz <= 2048;
- *   dx, dy, dz > 0; z_focus != z_ref and the image volume in front of the
- *   projection plane (z0 > z_ref, z_focus > z_ref);
- *   max_pos >= 0; tol in (0, 0.1] (target relative error of each NUFFT;
- *   0 selects 1e-4); upsample 0 (automatic = 2) or >= 2 (the lateral grid is
- *   the next power of two at or above upsample * n); kernel_width 0 (from tol)
- *   or 3..8 taps. */
+ *   n_tx, n_rx >= 1, n_tx * n_rx <= 4096; n_freq >= 1, freq_hz finite,
+ *   strictly increasing, > 0;
+ *   nx, ny, nz powers of two with 8 <= nx, ny <= 2048 and 2 <= nz <= 512;
+ *   dx, dy, dz > 0; the scene reference depth and the image volume in front
+ *   of the projection plane (z_focus > z_ref, z0 > z_ref);
+ *   0 <= max_pos and max_pos * n_tx * n_rx < 2^31;
+ *   tol 0 or in (0, 0.1]: target relative L2 error of the lateral NUFFT
+ *   (0 selects 1e-3); the kernel width is the smallest whose calibrated
+ *   error 5 exp(-pi W sqrt(1 - 1/sigma)) meets it;
+ *   upsample 0 (automatic = 2) or in [2, 4] (the lateral grid is the next power
+ *   of two at or above upsample * n; SAR_ERR_UNSUPPORTED otherwise);
+ *   kernel_width 0 (from tol) or 3..8 taps. */
 typedef struct {
   int32_t n_tx;
   int32_t n_rx;

@@ -36,10 +36,12 @@ def _compile(src):
     lang = ["-x", "hip"]
     extra = []
     if src.startswith("k_grid_w"):
-        # keep the unrolled per-offset bodies separate so the register tile of
-        # accumulators is never merged into a pointer phi (which would force it
-        # into scratch memory)
-        extra = ["-mllvm", "-simplifycfg-sink-common=false"]
+        # keep the unrolled per-offset bodies of the gridding dispatch as
+        # separate uniform branches: no sinking into a pointer phi (which would
+        # push the accumulator tile to scratch memory) and no structurisation of
+        # the uniform branch tree (which would add register copies on every path)
+        extra = ["-mllvm", "-simplifycfg-sink-common=false",
+                 "-mllvm", "-structurizecfg-skip-uniform-regions=true"]
     cmd = [HIPCC] + COMMON + extra + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -27,12 +27,22 @@ struct GeoArgs {
   double kb_beta, inv_i0_beta;
 };
 
+// 1/k^2 for the power series of I0 (multiplies instead of float64 divides)
+__constant__ double c_inv_k2[48] = {
+    0.0,          1.0,          1.0 / 4,      1.0 / 9,      1.0 / 16,     1.0 / 25,     1.0 / 36,
+    1.0 / 49,     1.0 / 64,     1.0 / 81,     1.0 / 100,    1.0 / 121,    1.0 / 144,    1.0 / 169,
+    1.0 / 196,    1.0 / 225,    1.0 / 256,    1.0 / 289,    1.0 / 324,    1.0 / 361,    1.0 / 400,
+    1.0 / 441,    1.0 / 484,    1.0 / 529,    1.0 / 576,    1.0 / 625,    1.0 / 676,    1.0 / 729,
+    1.0 / 784,    1.0 / 841,    1.0 / 900,    1.0 / 961,    1.0 / 1024,   1.0 / 1089,   1.0 / 1156,
+    1.0 / 1225,   1.0 / 1296,   1.0 / 1369,   1.0 / 1444,   1.0 / 1521,   1.0 / 1600,   1.0 / 1681,
+    1.0 / 1764,   1.0 / 1849,   1.0 / 1936,   1.0 / 2025,   1.0 / 2116,   1.0 / 2209};
+
+// Power series of the modified Bessel function of the first kind, order 0.
 __device__ __forceinline__ double bessel_i0(double x) {
-  // power series of the modified Bessel function of the first kind, order 0
   const double q = 0.25 * x * x;
   double term = 1.0, sum = 1.0;
-  for (int k = 1; k < 80; ++k) {
-    term *= q / ((double)k * (double)k);
+  for (int k = 1; k < 48; ++k) {
+    term *= q * c_inv_k2[k];
     sum += term;
     if (term < 1e-17 * sum) break;
   }
@@ -40,11 +50,11 @@ __device__ __forceinline__ double bessel_i0(double x) {
 }
 
 // Kaiser-Bessel kernel of width W (cells), normalised to 1 at the centre.
-__device__ __forceinline__ double kb_weight(double d, int W, double beta, double inv_i0_beta) {
+__device__ __forceinline__ float kb_weight(double d, int W, double beta, double inv_i0_beta) {
   const double z = 2.0 * d / (double)W;
   const double r = 1.0 - z * z;
-  if (r <= 0.0) return 0.0;
-  return bessel_i0(beta * sqrt(r)) * inv_i0_beta;
+  if (r <= 0.0) return 0.f;
+  return (float)(bessel_i0(beta * sqrt(r)) * inv_i0_beta);
 }
 
 // grid coordinate in [0, m) and first-tap cell for a kernel of width W
@@ -180,13 +190,10 @@ __global__ void k_scatter(int64_t n_v, const int32_t* __restrict__ key, const in
   order[start[key[n]] + rank[n]] = (int32_t)n;
 }
 
-// One thread per cell: order the cell's samples by source index, then write
-// their records (geometry recomputed in float64 from the shot position).
-template <int W>
-__global__ void k_records(GeoArgs a, const int32_t* __restrict__ start, int32_t* __restrict__ order,
-                          SampleRec<W>* __restrict__ rec) {
+// One thread per cell: order the cell's samples by source index.
+__global__ void k_sort_cells(int64_t ncell, const int32_t* __restrict__ start, int32_t* __restrict__ order) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= (int64_t)a.mx * a.my) return;
+  if (c >= ncell) return;
   const int s0 = start[c], s1 = start[c + 1];
   for (int i = s0 + 1; i < s1; ++i) {
     const int v = order[i];
@@ -197,29 +204,37 @@ __global__ void k_records(GeoArgs a, const int32_t* __restrict__ start, int32_t*
     }
     order[j + 1] = v;
   }
-  for (int s = s0; s < s1; ++s) {
-    const int64_t n = order[s];
-    const int64_t m = n / a.n_pair;
-    const int l = (int)(n - m * a.n_pair);
-    const double xv = a.pos[3 * m + 0] + a.pair[4 * l + 0];
-    const double yv = a.pos[3 * m + 1] + a.pair[4 * l + 1];
-    const double dzv = a.pos[3 * m + 2] - a.z_ref;
-    double gx, gy;
-    int cx, cy;
-    grid_coord(xv - a.xc, a.gsx, a.mx, W, gx, cx);
-    grid_coord(yv - a.yc, a.gsy, a.my, W, gy, cy);
-    SampleRec<W> r;
-    r.src = (int32_t)n;
-    r.cx = (int16_t)wrap(cx, a.mx);
-    r.cy = (int16_t)wrap(cy, a.my);
-    r.beta = a.beta_sign * dzv + a.pair[4 * l + 2];
+}
+
+// One thread per sorted slot: the record of the slot's sample, its geometry
+// recomputed in float64 from the shot position.
+template <int W>
+__global__ void k_records(GeoArgs a, const int32_t* __restrict__ order, SampleRec<W>* __restrict__ rec) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_v) return;
+  const int64_t n = order[s];
+  const int64_t m = n / a.n_pair;
+  const int l = (int)(n - m * a.n_pair);
+  const double xv = a.pos[3 * m + 0] + a.pair[4 * l + 0];
+  const double yv = a.pos[3 * m + 1] + a.pair[4 * l + 1];
+  const double dzv = a.pos[3 * m + 2] - a.z_ref;
+  double gx, gy;
+  int cx, cy;
+  grid_coord(xv - a.xc, a.gsx, a.mx, W, gx, cx);
+  grid_coord(yv - a.yc, a.gsy, a.my, W, gy, cy);
+  SampleRec<W> r;
+  r.src = (int32_t)n;
+  r.cx = (int16_t)wrap(cx, a.mx);
+  r.cy = (int16_t)wrap(cy, a.my);
+  r.beta = a.beta_sign * dzv + a.pair[4 * l + 2];
+  const double fx = (double)cx - gx;
+  const double fy = (double)cy - gy;
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-      r.wx[j] = (float)kb_weight((double)(cx + j) - gx, W, a.kb_beta, a.inv_i0_beta);
-      r.wy[j] = (float)kb_weight((double)(cy + j) - gy, W, a.kb_beta, a.inv_i0_beta);
-    }
-    rec[s] = r;
+  for (int j = 0; j < W; ++j) {
+    r.wx[j] = kb_weight(fx + j, W, a.kb_beta, a.inv_i0_beta);
+    r.wy[j] = kb_weight(fy + j, W, a.kb_beta, a.inv_i0_beta);
   }
+  rec[s] = r;
 }
 
 template <int W>
@@ -264,8 +279,8 @@ sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, co
   if (n_v > 0) {
     k_scatter<<<(unsigned)((n_v + tb - 1) / tb), tb, 0, stream>>>(n_v, ws.key, ws.rank, ws.cell_start,
                                                                   ws.order);
-    k_records<W><<<(unsigned)((ncell + tb - 1) / tb), tb, 0, stream>>>(a, ws.cell_start, ws.order,
-                                                                       (SampleRec<W>*)ws.rec);
+    k_sort_cells<<<(unsigned)((ncell + tb - 1) / tb), tb, 0, stream>>>(ncell, ws.cell_start, ws.order);
+    k_records<W><<<(unsigned)((n_v + tb - 1) / tb), tb, 0, stream>>>(a, ws.order, (SampleRec<W>*)ws.rec);
   }
   return check_hip(hipGetLastError(), "geometry/sort launch");
 }

@@ -10,7 +10,9 @@
 // whose W x W support touches the tile (rows of base cells, each a contiguous
 // run in the cell-sorted list), compensates the sample's echo once per
 // frequency with the float64 phase argument k * beta reduced modulo one cycle,
-// and adds the clipped separable taps.  Which taps of a sample land inside the
+// and adds the clipped separable taps.  Sample records are staged in LDS 64 at
+// a time (one lane per record) and read back as broadcasts; echo rows are
+// prefetched eight samples ahead into a ring of registers.  Which taps of a sample land inside the
 // tile depends on its base-cell offset (A, B) relative to the tile; a uniform
 // binary dispatch selects a fully unrolled body for that offset so every
 // accumulator index is static.  Tiles partition the grid, so each cell is
@@ -36,13 +38,6 @@ struct GridArgs {
   float2* grid;       // [my][mx][nf]
   int mx, my, nf;
   int ntx, nty;
-};
-
-template <int W>
-struct Cur {
-  SampleRec<W> r;
-  float2 e;
-  int a;  // row offset of the base cell relative to the tile
 };
 
 template <int LO, int HI, typename F>
@@ -73,7 +68,12 @@ template <int W, int ET>
 __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
   constexpr int NB = T + W - 1;       // base-cell offsets per axis touching a tile
   constexpr int NSEG = 2 * NB;        // each row may split in two at the x wrap
-  __shared__ int seg_s[NSEG], seg_e[NSEG];
+  constexpr int D = 8;                // echo prefetch depth (samples)
+  constexpr int RW = (int)(sizeof(SampleRec<W>) / sizeof(uint4));
+  static_assert(sizeof(SampleRec<W>) % sizeof(uint4) == 0, "record is a whole number of 16-byte words");
+  __shared__ int seg_s[NSEG];
+  __shared__ int seg_off[NSEG + 1];
+  __shared__ uint4 recs[64 * RW];     // records of the current chunk of 64 samples
 
   const uint32_t work = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = (int)(work % (uint32_t)a.ntx);
@@ -95,19 +95,33 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
     const int64_t row = (int64_t)cy * a.mx;
     const int xlo = tx0 - (W - 1);
     const int xhi = tx0 + T;
+    int s0, e0, s1 = 0, e1 = 0;
     if (xlo >= 0) {
-      seg_s[2 * lane] = a.cell_start[row + xlo];
-      seg_e[2 * lane] = a.cell_start[row + xhi];
-      seg_s[2 * lane + 1] = 0;
-      seg_e[2 * lane + 1] = 0;
+      s0 = a.cell_start[row + xlo];
+      e0 = a.cell_start[row + xhi];
     } else {
-      seg_s[2 * lane] = a.cell_start[row + a.mx + xlo];
-      seg_e[2 * lane] = a.cell_start[row + a.mx];
-      seg_s[2 * lane + 1] = a.cell_start[row];
-      seg_e[2 * lane + 1] = a.cell_start[row + xhi];
+      s0 = a.cell_start[row + a.mx + xlo];
+      e0 = a.cell_start[row + a.mx];
+      s1 = a.cell_start[row];
+      e1 = a.cell_start[row + xhi];
     }
+    seg_s[2 * lane] = s0;
+    seg_s[2 * lane + 1] = s1;
+    seg_off[2 * lane] = e0 - s0;
+    seg_off[2 * lane + 1] = e1 - s1;
   }
   __syncthreads();
+  if (lane == 0) {
+    int run = 0;
+    for (int k = 0; k < NSEG; ++k) {
+      const int l = seg_off[k];
+      seg_off[k] = run;
+      run += l;
+    }
+    seg_off[NSEG] = run;
+  }
+  __syncthreads();
+  const int total = __builtin_amdgcn_readfirstlane(seg_off[NSEG]);
 
   float2 acc[T][T];
 #pragma unroll
@@ -115,60 +129,78 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
 #pragma unroll
     for (int c = 0; c < T; ++c) acc[r][c] = make_float2(0.f, 0.f);
 
-  // walk all samples of all runs with a one-deep prefetch of record and echo
-  int seg = 0, s = 0, e = 0;
-  auto next_sample = [&]() __attribute__((always_inline)) -> bool {
-    ++s;
-    while (s >= e) {
-      if (++seg >= NSEG) return false;
-      s = __builtin_amdgcn_readfirstlane(seg_s[seg]);
-      e = __builtin_amdgcn_readfirstlane(seg_e[seg]);
+  for (int c0 = 0; c0 < total; c0 += 64) {
+    const int n_c = __builtin_amdgcn_readfirstlane(min(64, total - c0));
+    // lane j stages the record of the chunk's j-th sample in LDS
+    int srcv = 0, av = 0;
+    if (lane < n_c) {
+      const int t = c0 + lane;
+      int k = 0;
+      while (seg_off[k + 1] <= t) ++k;
+      const int s = seg_s[k] + (t - seg_off[k]);
+      const uint4* rp = (const uint4*)(rec + s);
+#pragma unroll
+      for (int q = 0; q < RW; ++q) recs[lane * RW + q] = rp[q];
+      srcv = rec[s].src;
+      av = k / 2 - (W - 1);
     }
-    return true;
-  };
-  seg = -1;
-  s = 0;
-  e = 0;
-  bool have = next_sample();
-  Cur<W> cur;
-  if (have) {
-    cur.r = rec[s];
-    cur.a = seg / 2 - (W - 1);
-    cur.e = load_echo<ET>(a.echo, (int64_t)cur.r.src * a.nf + fl, a.echo_scale);
-  }
-  while (have) {
-    const bool have_next = next_sample();
-    Cur<W> nxt;
-    if (have_next) {
-      nxt.r = rec[s];
-      nxt.a = seg / 2 - (W - 1);
-      nxt.e = load_echo<ET>(a.echo, (int64_t)nxt.r.src * a.nf + fl, a.echo_scale);
+    __syncthreads();
+
+    // echo prefetch ring (D samples ahead); slots are selected by a uniform
+    // switch so every ring register keeps a static index
+    float2 ring[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      ring[d] = make_float2(0.f, 0.f);
+      if (d < n_c) {
+        const int sd = __builtin_amdgcn_readlane(srcv, d);
+        ring[d] = load_echo<ET>(a.echo, (int64_t)sd * a.nf + fl, a.echo_scale);
+      }
     }
-    // compensation: s_hat = s exp(+j 2 pi f beta / c)
-    const float2 v = cmul(cur.e, cis_cycles(cur.r.beta * fcc));
-    int b = cur.r.cx - tx0;
-    if (b < -(W - 1)) b += a.mx;
-    if (b >= T) b -= a.mx;
-    const int idx = __builtin_amdgcn_readfirstlane((cur.a + (W - 1)) * NB + (b + (W - 1)));
-    dispatch_range<0, NB * NB>(idx, [&](auto ic) __attribute__((always_inline)) {
-      constexpr int I = decltype(ic)::value;
-      constexpr int A = I / NB - (W - 1);
-      constexpr int B = I % NB - (W - 1);
-      static_for<0, W>([&](auto jc) __attribute__((always_inline)) {
-        constexpr int j = decltype(jc)::value;
-        constexpr int r = A + j;
-        if constexpr (r >= 0 && r < T) {
-          const float2 vy = cscale(v, cur.r.wy[j]);
-          static_for<0, W>([&](auto kc) __attribute__((always_inline)) {
-            constexpr int k = decltype(kc)::value;
-            constexpr int c = B + k;
-            if constexpr (c >= 0 && c < T) cfma(acc[r][c], vy, cur.r.wx[k]);
-          });
-        }
+    for (int j = 0; j < n_c; ++j) {
+      const int jn = j + D;
+      const bool pre = jn < n_c;
+      const int sn = __builtin_amdgcn_readlane(srcv, pre ? jn : 0);
+      const int64_t en = (int64_t)sn * a.nf + fl;
+      float2 ev = make_float2(0.f, 0.f);
+      dispatch_range<0, D>(j & (D - 1), [&](auto dc) __attribute__((always_inline)) {
+        constexpr int d = decltype(dc)::value;
+        ev = ring[d];
+        if (pre) ring[d] = load_echo<ET>(a.echo, en, a.echo_scale);
       });
-    });
-    cur = nxt;
-    have = have_next;
+      SampleRec<W> r;
+      {
+        uint4 w4[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) w4[q] = recs[j * RW + q];
+        __builtin_memcpy(&r, w4, sizeof(r));
+      }
+      const int A = __builtin_amdgcn_readlane(av, j);
+      // compensation: s_hat = s exp(+j 2 pi f beta / c)
+      const float2 v = cmul(ev, cis_cycles(r.beta * fcc));
+      int b = __builtin_amdgcn_readfirstlane((int)r.cx) - tx0;
+      if (b < -(W - 1)) b += a.mx;
+      if (b >= T) b -= a.mx;
+      const int idx = (A + (W - 1)) * NB + (b + (W - 1));
+      dispatch_range<0, NB * NB>(idx, [&](auto ic) __attribute__((always_inline)) {
+        constexpr int I = decltype(ic)::value;
+        constexpr int AA = I / NB - (W - 1);
+        constexpr int BB = I % NB - (W - 1);
+        static_for<0, W>([&](auto jc) __attribute__((always_inline)) {
+          constexpr int jj = decltype(jc)::value;
+          constexpr int rr = AA + jj;
+          if constexpr (rr >= 0 && rr < T) {
+            const float2 vy = cscale(v, r.wy[jj]);
+            static_for<0, W>([&](auto kc) __attribute__((always_inline)) {
+              constexpr int kk = decltype(kc)::value;
+              constexpr int cc = BB + kk;
+              if constexpr (cc >= 0 && cc < T) cfma(acc[rr][cc], vy, r.wx[kk]);
+            });
+          }
+        });
+      });
+    }
+    __syncthreads();
   }
 
   if (active) {

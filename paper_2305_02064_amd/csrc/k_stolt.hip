@@ -6,13 +6,18 @@
 // S k_z exp(-j k_z Z_0) (Eq. (15), P = 1).  The Stolt map plus the inverse
 // transform along z is the non-uniform sum
 //   Z(z_w) = sum_i F_i exp(+j k_z,i z_w),  z_w = z0 + w dz,
-// a 1-D type-1 NUFFT at the positions theta_i = k_z,i dz.  Each column is
-// handled by one wavefront: float64 pre-phase exp(j k_z (z_mid - Z_0)) and
-// grid position, exponential-of-semicircle spreading into an oversampled LDS
-// grid of MZ cells, an inverse radix-4 Stockham FFT in LDS, and
-// deapodisation of the nz centred outputs.  The +-1 factor (-1)^(P+Q) that
-// lets the next step use plain inverse DFTs on centred mode indices is
-// folded in here.
+// a 1-D type-1 NUFFT at the positions theta_i = k_z,i dz: float64 pre-phase
+// exp(j k_z (z_mid - Z_0)) and grid position, exponential-of-semicircle
+// spreading into an oversampled LDS grid of MZ cells, an inverse four-step
+// FFT in registers with one LDS exchange, and deapodisation of the nz centred
+// outputs.
+//
+// A column is handled by a group of 16 lanes (4 columns per wavefront).  Each
+// lane takes a contiguous run of frequencies, whose k_z positions are
+// monotone and close together, accumulates them in a small register window of
+// cells and flushes it to the shared grid with LDS atomics, so few lanes hit
+// the same cell at once.  The +-1 factor (-1)^(P+Q) that lets the next step
+// use plain inverse DFTs on centred mode indices is folded in here.
 
 #include "device_common.hpp"
 #include "sar_internal.hpp"
@@ -20,7 +25,9 @@
 namespace sar {
 namespace {
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 4;   // wavefronts per block
+constexpr int kG = 16;      // lanes per column
+constexpr int kCols = kWaves * 64 / kG;  // columns per block
 
 struct StoltArgs {
   const float2* spec;  // [ny][nx][nf]
@@ -36,115 +43,131 @@ struct StoltArgs {
   int64_t ncol;
 };
 
-// Stockham autosort FFT (sign +) of n = MZ points held in LDS, executed by
-// the 64 lanes of one wavefront; returns the buffer holding the result.
-template <int MZ>
-__device__ float2* wave_ifft(float2* x, float2* y, const float2* __restrict__ tw, int lane) {
-  constexpr int LOG = ct_log2(MZ);
-  int ns = 1;
-  if constexpr (LOG & 1) {  // one radix-2 stage first
-    for (int j = lane; j < MZ / 2; j += 64) {
-      const float2 a0 = x[j], a1 = x[j + MZ / 2];
-      y[2 * j] = cadd(a0, a1);
-      y[2 * j + 1] = csub(a0, a1);
-    }
-    __syncthreads();
-    float2* t = x;
-    x = y;
-    y = t;
-    ns = 2;
-  }
-  for (; ns < MZ; ns *= 4) {
-    for (int j = lane; j < MZ / 4; j += 64) {
-      const int k = j & (ns - 1);
-      const int step = MZ / (4 * ns);
-      const float2 w1 = tw[k * step];
-      const float2 w2 = tw[2 * k * step];
-      const float2 w3 = tw[3 * k * step];
-      const float2 a0 = x[j];
-      const float2 a1 = cmul(x[j + MZ / 4], w1);
-      const float2 a2 = cmul(x[j + MZ / 2], w2);
-      const float2 a3 = cmul(x[j + 3 * MZ / 4], w3);
-      const float2 b0 = cadd(a0, a2), b1 = csub(a0, a2), b2 = cadd(a1, a3);
-      const float2 d = csub(a1, a3);
-      const float2 b3 = make_float2(-d.y, d.x);  // +j (a1 - a3)
-      const int base = (j / ns) * 4 * ns + k;
-      y[base] = cadd(b0, b2);
-      y[base + ns] = cadd(b1, b3);
-      y[base + 2 * ns] = csub(b0, b2);
-      y[base + 3 * ns] = csub(b1, b3);
-    }
-    __syncthreads();
-    float2* t = x;
-    x = y;
-    y = t;
-  }
-  return x;
+// exponential-of-semicircle kernel of width WZ at signed distance d (cells)
+template <int WZ>
+__device__ __forceinline__ float es_weight(float d, float beta) {
+  const float z = d * (2.f / (float)WZ);
+  const float q = 1.f - z * z;
+  return q > 0.f ? __expf(beta * (__builtin_sqrtf(q) - 1.f)) : 0.f;
 }
 
 template <int MZ, int WZ>
 __global__ __launch_bounds__(64 * kWaves) void k_stolt(StoltArgs a) {
-  __shared__ float2 buf[kWaves][2][MZ];
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int64_t col = (int64_t)blockIdx.x * kWaves + wave;
-  const bool live = col < a.ncol;
-  const int64_t colc = live ? col : 0;
-  const int Q = (int)(colc / a.nx);
-  const int P = (int)(colc - (int64_t)Q * a.nx);
-  float2* g0 = buf[wave][0];
-  float2* g1 = buf[wave][1];
-  for (int c = lane; c < MZ; c += 64) g0[c] = make_float2(0.f, 0.f);
-  __syncthreads();
+  constexpr int L2 = MZ / kG;       // points per lane in the first FFT pass
+  constexpr int WWIN = WZ + 2;      // register window of cells per lane
+  static_assert(MZ % kG == 0 && MZ <= 1024, "Stolt grid of 64..1024 cells");
+  __shared__ float2 grid[kCols][MZ];
+  __shared__ float2 tw[MZ];
+  __shared__ float deap[1024];
+  for (int i = threadIdx.x; i < MZ; i += 64 * kWaves) tw[i] = a.tw[i];
+  for (int i = threadIdx.x; i < a.nz; i += 64 * kWaves) deap[i] = a.deapz[i];
+  const int cl = threadIdx.x / kG;   // column slot in the block
+  const int gl = threadIdx.x % kG;   // lane within the column's group
+  float2* g = grid[cl];
+  const int per = (a.nf + kG - 1) / kG;  // contiguous frequencies per lane
+  const int64_t ngroups = (a.ncol + kCols - 1) / kCols;
 
-  if (live) {
-    const double kx = (double)(P - a.nx / 2) * a.dkx;
-    const double ky = (double)(Q - a.ny / 2) * a.dky;
-    const double kp2 = kx * kx + ky * ky;
-    const float sgn = ((P + Q) & 1) ? -1.f : 1.f;
-    const float2* __restrict__ sp = a.spec + colc * a.nf;
-    // lane l takes a contiguous run of frequencies so that lanes of one
-    // instruction land on different cells of the (monotone) k_z axis
-    const int per = (a.nf + 63) / 64;
-    for (int r = 0; r < per; ++r) {
-      const int i = lane * per + r;
-      if (i >= a.nf) break;
-      const double k = a.k[i];
-      const double kz2 = 4.0 * k * k - kp2;
-      if (kz2 <= 0.0) continue;
-      const double kz = sqrt(kz2);
-      const float2 s = sp[i];
-      const float2 ph = cis_cycles(kz * a.zmid_minus_zref_cyc);
-      const float2 v = cscale(cmul(s, ph), (float)kz * sgn);
-      double g = kz * a.dz_cells;
-      g -= floor(g / (double)MZ) * (double)MZ;
-      const int c0 = (int)floor(g - 0.5 * WZ) + 1;
-      const float d0 = (float)((double)c0 - g);
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t col = grp * kCols + cl;
+    const bool live = col < a.ncol;
+    const int64_t colc = live ? col : 0;
+    const int Q = (int)(colc / a.nx);
+    const int P = (int)(colc - (int64_t)Q * a.nx);
+    for (int c = gl; c < MZ; c += kG) g[c] = make_float2(0.f, 0.f);
+    __syncthreads();
+
+    // spreading: each lane accumulates its run of samples in a register window
+    // of WWIN cells starting at cell wb and flushes it with LDS atomics when a
+    // sample's support leaves the window
+    if (live) {
+      const double kx = (double)(P - a.nx / 2) * a.dkx;
+      const double ky = (double)(Q - a.ny / 2) * a.dky;
+      const double kp2 = kx * kx + ky * ky;
+      const float sgn = ((P + Q) & 1) ? -1.f : 1.f;
+      const float2* __restrict__ sp = a.spec + colc * a.nf;
+      float2 win[WWIN];
 #pragma unroll
-      for (int j = 0; j < WZ; ++j) {
-        const float z = 2.f * (d0 + (float)j) / (float)WZ;
-        const float q = 1.f - z * z;
-        const float wgt = q > 0.f ? __expf(a.es_beta * (__builtin_sqrtf(q) - 1.f)) : 0.f;
-        const int c = (c0 + j) & (MZ - 1);
-        atomicAdd(&g0[c].x, v.x * wgt);
-        atomicAdd(&g0[c].y, v.y * wgt);
+      for (int s2 = 0; s2 < WWIN; ++s2) win[s2] = make_float2(0.f, 0.f);
+      int wb = 0;
+      bool open = false;
+      auto flush = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int s2 = 0; s2 < WWIN; ++s2) {
+          if (win[s2].x != 0.f || win[s2].y != 0.f) {
+            const int c = (wb + s2) & (MZ - 1);
+            atomicAdd(&g[c].x, win[s2].x);
+            atomicAdd(&g[c].y, win[s2].y);
+          }
+          win[s2] = make_float2(0.f, 0.f);
+        }
+      };
+      for (int r = 0; r < per; ++r) {
+        const int i = gl * per + r;
+        if (i >= a.nf) break;
+        const double k = a.k[i];
+        const double kz2 = 4.0 * k * k - kp2;
+        if (kz2 <= 0.0) continue;
+        const double kz = sqrt(kz2);
+        const float2 sv = sp[i];
+        const float2 ph = cis_cycles(kz * a.zmid_minus_zref_cyc);
+        const float2 v = cscale(cmul(sv, ph), (float)kz * sgn);
+        const double gc = kz * a.dz_cells;  // grid position (cells), not wrapped
+        const int c0 = (int)floor(gc - 0.5 * WZ) + 1;
+        if (!open || c0 < wb || c0 + WZ > wb + WWIN) {
+          if (open) flush();
+          wb = c0;
+          open = true;
+        }
+        const float d0 = (float)((double)wb - gc);
+#pragma unroll
+        for (int s2 = 0; s2 < WWIN; ++s2) {
+          const float wgt = es_weight<WZ>(d0 + (float)s2, a.es_beta);
+          cfma(win[s2], v, wgt);
+        }
+      }
+      if (open) flush();
+    }
+    __syncthreads();
+
+    // inverse DFT of the MZ cells: four-step with L1 = 16 lanes x L2 points
+    // X[k2 + L2 k1] = sum_l1 w_16^(l1 k1) w_MZ^(l1 k2) sum_l2 x[l1 + 16 l2] w_L2^(l2 k2)
+    float2 v1[L2];
+#pragma unroll
+    for (int l2 = 0; l2 < L2; ++l2) v1[l2] = g[gl + kG * l2];
+    reg_dft_dif<L2, +1>(v1);
+    __syncthreads();
+    static_for<0, L2>([&](auto kc) __attribute__((always_inline)) {
+      constexpr int k2 = decltype(kc)::value;
+      float2 y = v1[ct_bitrev(k2, ct_log2(L2))];
+      if constexpr (k2 != 0) y = cmul(y, tw[gl * k2]);
+      g[gl * L2 + k2] = y;   // [l1][k2]
+    });
+    __syncthreads();
+    if (live) {
+      float2* __restrict__ out = a.zc + colc * a.nz;
+      const int h = a.nz / 2;
+      for (int k2 = gl; k2 < L2; k2 += kG) {
+        float2 v2[kG];
+#pragma unroll
+        for (int l1 = 0; l1 < kG; ++l1) v2[l1] = g[l1 * L2 + k2];
+        reg_dft_dif<kG, +1>(v2);
+        static_for<0, kG>([&](auto kc) __attribute__((always_inline)) {
+          constexpr int k1 = decltype(kc)::value;
+          const int kk = k2 + L2 * k1;
+          const int w = kk < h ? kk + h : (kk >= MZ - h ? kk - MZ + h : -1);
+          if (w >= 0) out[w] = cscale(v2[ct_bitrev(k1, ct_log2(kG))], deap[w]);
+        });
       }
     }
-  }
-  __syncthreads();
-  const float2* res = wave_ifft<MZ>(g0, g1, a.tw, lane);
-  if (live) {
-    float2* __restrict__ out = a.zc + colc * a.nz;
-    for (int w = lane; w < a.nz; w += 64) {
-      const int m = w - a.nz / 2;
-      out[w] = cscale(res[m & (MZ - 1)], a.deapz[w]);
-    }
+    __syncthreads();
   }
 }
 
 template <int MZ>
 sar_status stolt_mz(const Plan& p, const StoltArgs& a, hipStream_t stream) {
-  const int64_t nblk = (a.ncol + kWaves - 1) / kWaves;
+  // enough blocks to fill every CU several times over; each loops over groups
+  const int64_t ngroups = (a.ncol + kCols - 1) / kCols;
+  const int64_t nblk = ngroups < 256 * 8 ? ngroups : 256 * 8;
   switch (p.wz) {
     case 6: k_stolt<MZ, 6><<<(unsigned)nblk, 64 * kWaves, 0, stream>>>(a); break;
     case 8: k_stolt<MZ, 8><<<(unsigned)nblk, 64 * kWaves, 0, stream>>>(a); break;
@@ -180,7 +203,6 @@ sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, hipStr
     case 256: return stolt_mz<256>(p, a, stream);
     case 512: return stolt_mz<512>(p, a, stream);
     case 1024: return stolt_mz<1024>(p, a, stream);
-    case 2048: return stolt_mz<2048>(p, a, stream);
     default: return fail(SAR_ERR_UNSUPPORTED, "Stolt grid size not supported");
   }
 }
