@@ -10,9 +10,12 @@
 // whose W x W support touches the tile (rows of base cells, each a contiguous
 // run in the cell-sorted list), compensates the sample's echo once per
 // frequency with the float64 phase argument k * beta reduced modulo one cycle,
-// and adds the clipped separable taps.  Sample records are staged in LDS 64 at
-// a time (one lane per record) and read back as broadcasts; echo rows are
-// prefetched eight samples ahead into a ring of registers.  Which taps of a sample land inside the
+// and adds the clipped separable taps.  Echo rows are streamed through LDS in
+// chunks of 8 samples with the direct global-to-LDS loads of gfx950: at the
+// start of chunk c the wave waits once, moves the chunk's echo values into
+// registers, and issues the loads of chunk c+1 (whose source rows were fetched
+// a chunk earlier), so memory latency overlaps the arithmetic of a whole
+// chunk.  Sample records arrive through scalar loads.  Which taps of a sample land inside the
 // tile depends on its base-cell offset (A, B) relative to the tile; a uniform
 // binary dispatch selects a fully unrolled body for that offset so every
 // accumulator index is static.  Tiles partition the grid, so each cell is
@@ -32,6 +35,7 @@ constexpr int T = kTile;
 struct GridArgs {
   const void* rec;
   const int32_t* cell_start;
+  const int32_t* order;  // source row of each sorted sample
   const void* echo;
   float echo_scale;
   const double* fcc;  // f / c per frequency
@@ -64,16 +68,21 @@ __device__ __forceinline__ float2 load_echo(const void* echo, int64_t idx, float
   }
 }
 
+// asynchronous copy of one dword per lane from global memory into LDS at
+// lds_base + 4 * lane (the direct global-to-LDS load of gfx950)
+__device__ __forceinline__ void dma_dword(const void* src, void* lds_base) {
+  __builtin_amdgcn_global_load_lds(src, (void __attribute__((address_space(3)))*)lds_base, 4, 0, 0);
+}
+
 template <int W, int ET>
 __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
   constexpr int NB = T + W - 1;       // base-cell offsets per axis touching a tile
   constexpr int NSEG = 2 * NB;        // each row may split in two at the x wrap
-  constexpr int D = 8;                // echo prefetch depth (samples)
-  constexpr int RW = (int)(sizeof(SampleRec<W>) / sizeof(uint4));
-  static_assert(sizeof(SampleRec<W>) % sizeof(uint4) == 0, "record is a whole number of 16-byte words");
+  constexpr int CH = 8;               // samples per pipeline chunk
+  constexpr int EB = ET == SAR_ECHO_C64 ? 512 : 256;  // echo bytes per sample and wave
   __shared__ int seg_s[NSEG];
   __shared__ int seg_off[NSEG + 1];
-  __shared__ uint4 recs[64 * RW];     // records of the current chunk of 64 samples
+  __shared__ __attribute__((aligned(16))) char echobuf[CH * EB];
 
   const uint32_t work = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = (int)(work % (uint32_t)a.ntx);
@@ -82,11 +91,25 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
   const int fchunk = (int)(rest / (uint32_t)a.nty);
   const int tx0 = tx * T, ty0 = ty * T;
   const int lane = threadIdx.x;
-  const int f = fchunk * 64 + lane;
+  const int fbase = fchunk * 64;
+  const int f = fbase + lane;
   const bool active = f < a.nf;
   const int fl = active ? f : a.nf - 1;
   const double fcc = a.fcc[fl];
-  const SampleRec<W>* __restrict__ rec = (const SampleRec<W>*)a.rec;
+  // records are read-only here: read through the constant address space they
+  // are fetched with scalar loads
+  typedef const __attribute__((address_space(4))) uint32_t* cword_ptr;
+  const cword_ptr crec = (cword_ptr)a.rec;
+  auto load_rec = [&](int sidx) __attribute__((always_inline)) {
+    constexpr int RD = (int)(sizeof(SampleRec<W>) / 4);
+    uint32_t w[RD];
+    const cword_ptr p = crec + (int64_t)sidx * RD;
+#pragma unroll
+    for (int q = 0; q < RD; ++q) w[q] = p[q];
+    SampleRec<W> out;
+    __builtin_memcpy(&out, w, sizeof(out));
+    return out;
+  };
 
   // runs of base cells: row j (A = j - (W-1)), x in [tx0 - (W-1), tx0 + T)
   if (lane < NB) {
@@ -122,6 +145,35 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
   }
   __syncthreads();
   const int total = __builtin_amdgcn_readfirstlane(seg_off[NSEG]);
+  const int nchunk = (total + CH - 1) / CH;
+
+  // sorted-list index of the chunk's lane-th sample (lanes >= chunk size: -1)
+  auto chunk_index = [&](int c) __attribute__((always_inline)) -> int {
+    const int t = c * CH + lane;
+    if (lane >= CH || t >= total) return -1;
+    int k = 0;
+    while (seg_off[k + 1] <= t) ++k;
+    return seg_s[k] + (t - seg_off[k]);
+  };
+  // echo rows of a chunk into LDS with direct global-to-LDS loads
+  auto stage_echo = [&](int c, int srcv) __attribute__((always_inline)) {
+    const int n = min(CH, total - c * CH);
+    for (int k = 0; k < n; ++k) {
+      const int src = __builtin_amdgcn_readlane(srcv, k);
+      if constexpr (ET == SAR_ECHO_C64) {
+        const float* row = (const float*)a.echo + (int64_t)src * a.nf * 2;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int fi = fbase * 2 + h * 64 + lane;   // float index within the row
+          dma_dword(row + (fi < 2 * a.nf ? fi : 0), echobuf + k * EB + h * 256);
+        }
+      } else {
+        const uint32_t* row = (const uint32_t*)a.echo + (int64_t)src * a.nf;
+        const int fi = fbase + lane;
+        dma_dword(row + (fi < a.nf ? fi : 0), echobuf + k * EB);
+      }
+    }
+  };
 
   float2 acc[T][T];
 #pragma unroll
@@ -129,59 +181,58 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
 #pragma unroll
     for (int c = 0; c < T; ++c) acc[r][c] = make_float2(0.f, 0.f);
 
-  for (int c0 = 0; c0 < total; c0 += 64) {
-    const int n_c = __builtin_amdgcn_readfirstlane(min(64, total - c0));
-    // lane j stages the record of the chunk's j-th sample in LDS
-    int srcv = 0, av = 0;
-    if (lane < n_c) {
-      const int t = c0 + lane;
-      int k = 0;
-      while (seg_off[k + 1] <= t) ++k;
-      const int s = seg_s[k] + (t - seg_off[k]);
-      const uint4* rp = (const uint4*)(rec + s);
-#pragma unroll
-      for (int q = 0; q < RW; ++q) recs[lane * RW + q] = rp[q];
-      srcv = rec[s].src;
-      av = k / 2 - (W - 1);
-    }
+  // pipeline: echo of chunk c+1 and source rows of chunk c+2 are in flight
+  // while chunk c is processed from registers
+  int sidx0 = chunk_index(0);
+  int sidx1 = chunk_index(1);
+  int src0 = sidx0 >= 0 ? a.order[sidx0] : 0;
+  int src1 = sidx1 >= 0 ? a.order[sidx1] : 0;
+  if (nchunk > 0) stage_echo(0, src0);
+  for (int c = 0; c < nchunk; ++c) {
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-
-    // echo prefetch ring (D samples ahead); slots are selected by a uniform
-    // switch so every ring register keeps a static index
-    float2 ring[D];
+    const int n = __builtin_amdgcn_readfirstlane(min(CH, total - c * CH));
+    // the chunk's echo values (re, im interleaved) in one register vector,
+    // indexed below with a uniform sample index
+    typedef float evec __attribute__((ext_vector_type(2 * CH)));
+    evec ev;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      ring[d] = make_float2(0.f, 0.f);
-      if (d < n_c) {
-        const int sd = __builtin_amdgcn_readlane(srcv, d);
-        ring[d] = load_echo<ET>(a.echo, (int64_t)sd * a.nf + fl, a.echo_scale);
+    for (int k = 0; k < CH; ++k) {
+      float2 t2;
+      if constexpr (ET == SAR_ECHO_C64) {
+        t2 = *(const float2*)(echobuf + k * EB + lane * 8);
+      } else {
+        t2 = __half22float2(*(const __half2*)(echobuf + k * EB + lane * 4));
+        t2 = make_float2(t2.x * a.echo_scale, t2.y * a.echo_scale);
       }
+      ev[2 * k] = t2.x;
+      ev[2 * k + 1] = t2.y;
     }
-    for (int j = 0; j < n_c; ++j) {
-      const int jn = j + D;
-      const bool pre = jn < n_c;
-      const int sn = __builtin_amdgcn_readlane(srcv, pre ? jn : 0);
-      const int64_t en = (int64_t)sn * a.nf + fl;
-      float2 ev = make_float2(0.f, 0.f);
-      dispatch_range<0, D>(j & (D - 1), [&](auto dc) __attribute__((always_inline)) {
-        constexpr int d = decltype(dc)::value;
-        ev = ring[d];
-        if (pre) ring[d] = load_echo<ET>(a.echo, en, a.echo_scale);
-      });
-      SampleRec<W> r;
-      {
-        uint4 w4[RW];
-#pragma unroll
-        for (int q = 0; q < RW; ++q) w4[q] = recs[j * RW + q];
-        __builtin_memcpy(&r, w4, sizeof(r));
-      }
-      const int A = __builtin_amdgcn_readlane(av, j);
-      // compensation: s_hat = s exp(+j 2 pi f beta / c)
-      const float2 v = cmul(ev, cis_cycles(r.beta * fcc));
-      int b = __builtin_amdgcn_readfirstlane((int)r.cx) - tx0;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (c + 1 < nchunk) stage_echo(c + 1, src1);
+    const int sidx2 = chunk_index(c + 2);
+    const int src2 = sidx2 >= 0 ? a.order[sidx2] : 0;
+    SampleRec<W> r = load_rec(__builtin_amdgcn_readlane(sidx0, 0));
+    for (int k = 0; k < n; ++k) {
+      // consume the current record (its scalar load was issued one sample ago)
+      int A = (int)r.cy - ty0;
+      if (A < -(W - 1)) A += a.my;
+      if (A >= T) A -= a.my;
+      int b = (int)r.cx - tx0;
       if (b < -(W - 1)) b += a.mx;
       if (b >= T) b -= a.mx;
-      const int idx = (A + (W - 1)) * NB + (b + (W - 1));
+      const int idx = __builtin_amdgcn_readfirstlane((A + (W - 1)) * NB + (b + (W - 1)));
+      const double arg = r.beta * fcc;
+      const SampleRec<W> rc = r;
+      // scalar loads return out of order and can only be waited for all
+      // together: issue the next record's load only after the current one
+      // has been consumed
+      asm volatile("" ::: "memory");
+      if (k + 1 < n) r = load_rec(__builtin_amdgcn_readlane(sidx0, k + 1));
+      const float2 e = make_float2(ev[2 * k], ev[2 * k + 1]);
+      // compensation: s_hat = s exp(+j 2 pi f beta / c)
+      const float2 v = cmul(e, cis_cycles(arg));
       dispatch_range<0, NB * NB>(idx, [&](auto ic) __attribute__((always_inline)) {
         constexpr int I = decltype(ic)::value;
         constexpr int AA = I / NB - (W - 1);
@@ -190,17 +241,19 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
           constexpr int jj = decltype(jc)::value;
           constexpr int rr = AA + jj;
           if constexpr (rr >= 0 && rr < T) {
-            const float2 vy = cscale(v, r.wy[jj]);
+            const float2 vy = cscale(v, rc.wy[jj]);
             static_for<0, W>([&](auto kc) __attribute__((always_inline)) {
               constexpr int kk = decltype(kc)::value;
               constexpr int cc = BB + kk;
-              if constexpr (cc >= 0 && cc < T) cfma(acc[rr][cc], vy, r.wx[kk]);
+              if constexpr (cc >= 0 && cc < T) cfma(acc[rr][cc], vy, rc.wx[kk]);
             });
           }
         });
       });
     }
-    __syncthreads();
+    sidx0 = sidx1;
+    sidx1 = sidx2;
+    src1 = src2;
   }
 
   if (active) {
@@ -218,6 +271,7 @@ sar_status grid_w(const Plan& p, const void* d_echo, float echo_scale, const Wor
   GridArgs a;
   a.rec = ws.rec;
   a.cell_start = ws.cell_start;
+  a.order = ws.order;
   a.echo = d_echo;
   a.echo_scale = echo_scale;
   a.fcc = p.d_fcc;
