@@ -224,8 +224,8 @@ __global__ void k_records(GeoArgs a, const int32_t* __restrict__ order, SampleRe
   grid_coord(yv - a.yc, a.gsy, a.my, W, gy, cy);
   SampleRec<W> r;
   r.src = (int32_t)n;
-  r.cx = (int16_t)wrap(cx, a.mx);
-  r.cy = (int16_t)wrap(cy, a.my);
+  r.cx = (int16_t)wrap(wrap(cx, a.mx) + W - 1, a.mx);
+  r.cy = (int16_t)wrap(wrap(cy, a.my) + W - 1, a.my);
   r.beta = a.beta_sign * dzv + a.pair[4 * l + 2];
   const double fx = (double)cx - gx;
   const double fy = (double)cy - gy;

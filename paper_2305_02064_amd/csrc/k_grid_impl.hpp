@@ -1,28 +1,36 @@
-#pragma once
-// Steps a1 + a2 (kernel template; one translation unit per kernel width): multi-planar multistatic compensation (Eq. (11)) fused into
-// Kaiser-Bessel gridding of the irregular virtual samples onto the oversampled
-// uniform (x', y') grid (the spreading half of the type-1 NUFFT that stands in
-// for FT_2D of Eq. (16), Sec. III).
+// Steps a1 + a2 (kernel template; one translation unit per kernel width):
+// multi-planar multistatic compensation (Eq. (11)) fused into Kaiser-Bessel
+// gridding of the irregular virtual samples onto the oversampled uniform
+// (x', y') grid (the spreading half of the type-1 NUFFT that stands in for
+// FT_2D of Eq. (16), Sec. III).
 //
-// Output-stationary design: one wavefront owns an 8 x 8 tile of grid cells for
-// 64 consecutive frequencies (lane = frequency) and keeps the 64 complex
-// accumulators in registers.  It walks the sorted records of every sample
-// whose W x W support touches the tile (rows of base cells, each a contiguous
-// run in the cell-sorted list), compensates the sample's echo once per
-// frequency with the float64 phase argument k * beta reduced modulo one cycle,
-// and adds the clipped separable taps.  Echo rows are streamed through LDS in
-// chunks of 8 samples with the direct global-to-LDS loads of gfx950: at the
-// start of chunk c the wave waits once, moves the chunk's echo values into
-// registers, and issues the loads of chunk c+1 (whose source rows were fetched
-// a chunk earlier), so memory latency overlaps the arithmetic of a whole
-// chunk.  Sample records arrive through scalar loads.  Which taps of a sample land inside the
-// tile depends on its base-cell offset (A, B) relative to the tile; a uniform
-// binary dispatch selects a fully unrolled body for that offset so every
-// accumulator index is static.  Tiles partition the grid, so each cell is
-// written exactly once with plain coalesced stores: no atomics, no zeroing
-// pass, and a fixed summation order.
+// Output-stationary design: one wavefront owns a tile of 4 x 8 grid cells for
+// 128 frequencies; lane l carries frequencies fbase + l and fbase + 64 + l and
+// keeps 2 x 32 complex accumulators in registers.  It walks every sample
+// whose W x W support touches the tile (rows of first-tap cells, each a
+// contiguous run in the cell-sorted list), compensates the sample's echo with
+// the float64 phase argument k * beta reduced modulo one cycle, and adds the
+// clipped separable taps.  Which taps land inside the tile depends on the
+// sample's cell offset (A, B) relative to the tile; a uniform binary dispatch
+// selects a fully unrolled body for that offset, so every accumulator index is
+// static.  Tiles partition the grid, so each cell is written exactly once with
+// plain coalesced stores: no atomics, no zeroing pass, a fixed summation order.
+//
+// Echo rows are streamed through LDS in chunks of 8 samples with the direct
+// global-to-LDS loads of gfx950: at the start of chunk c the wave waits once,
+// moves the chunk's echo values into a register vector (indexed with the
+// uniform sample index), and issues the loads of chunk c+1, whose source rows
+// were fetched a chunk earlier.  Residual paths and cell offsets of a chunk
+// are gathered lane-parallel a chunk ahead, so all of its compensation phases
+// are computed together at the chunk start; kernel weights arrive through
+// scalar loads one sample ahead.  Carrying two
+// frequencies per lane spreads each sample visit's scalar work (dispatch,
+// weights) over twice the arithmetic.
+#pragma once
 
 #include <hip/hip_fp16.h>
+
+#include <cstddef>
 
 #include "device_common.hpp"
 #include "sar_internal.hpp"
@@ -30,7 +38,9 @@
 namespace sar {
 namespace grid_impl {
 
-constexpr int T = kTile;
+constexpr int TX = kTileX;
+constexpr int TY = kTileY;
+constexpr int FPL = 2;  // frequencies per lane
 
 struct GridArgs {
   const void* rec;
@@ -57,67 +67,59 @@ __device__ __forceinline__ void dispatch_range(int idx, F&& f) {
   }
 }
 
-template <int ET>
-__device__ __forceinline__ float2 load_echo(const void* echo, int64_t idx, float scale) {
-  if constexpr (ET == SAR_ECHO_C64) {
-    return ((const float2*)echo)[idx];
-  } else {
-    const __half2 h = ((const __half2*)echo)[idx];
-    const float2 v = __half22float2(h);
-    return make_float2(v.x * scale, v.y * scale);
-  }
+// value of lane k of a float64 register pair
+__device__ __forceinline__ double readlane_f64(double v, int k) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// asynchronous copy of one dword per lane from global memory into LDS at
-// lds_base + 4 * lane (the direct global-to-LDS load of gfx950)
+// asynchronous copies from global memory into LDS (the direct global-to-LDS
+// loads of gfx950): one dword, or 16 bytes, per lane to lds_base + size * lane
 __device__ __forceinline__ void dma_dword(const void* src, void* lds_base) {
   __builtin_amdgcn_global_load_lds(src, (void __attribute__((address_space(3)))*)lds_base, 4, 0, 0);
+}
+__device__ __forceinline__ void dma_quad(const void* src, void* lds_base) {
+  __builtin_amdgcn_global_load_lds(src, (void __attribute__((address_space(3)))*)lds_base, 16, 0, 0);
 }
 
 template <int W, int ET>
 __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
-  constexpr int NB = T + W - 1;       // base-cell offsets per axis touching a tile
-  constexpr int NSEG = 2 * NB;        // each row may split in two at the x wrap
+  constexpr int NBX = TX + W - 1;     // last-tap column offsets touching a tile
+  constexpr int NBY = TY + W - 1;     // last-tap row offsets touching a tile
+  constexpr int NSEG = 2 * NBY;       // each row of cells may split at the x wrap
   constexpr int CH = 8;               // samples per pipeline chunk
-  constexpr int EB = ET == SAR_ECHO_C64 ? 512 : 256;  // echo bytes per sample and wave
+  constexpr int EBH = ET == SAR_ECHO_C64 ? 512 : 256;  // echo bytes per sample, per 64 frequencies
+  constexpr int EB = FPL * EBH;
   __shared__ int seg_s[NSEG];
   __shared__ int seg_off[NSEG + 1];
   __shared__ __attribute__((aligned(16))) char echobuf[CH * EB];
 
+  // row-major tile order (x fastest, frequency chunk slowest); measured
+  // faster than narrower strip orders for the serpentine scans
   const uint32_t work = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = (int)(work % (uint32_t)a.ntx);
   const uint32_t rest = work / (uint32_t)a.ntx;
   const int ty = (int)(rest % (uint32_t)a.nty);
   const int fchunk = (int)(rest / (uint32_t)a.nty);
-  const int tx0 = tx * T, ty0 = ty * T;
+  const int tx0 = tx * TX, ty0 = ty * TY;
   const int lane = threadIdx.x;
-  const int fbase = fchunk * 64;
-  const int f = fbase + lane;
-  const bool active = f < a.nf;
-  const int fl = active ? f : a.nf - 1;
-  const double fcc = a.fcc[fl];
-  // records are read-only here: read through the constant address space they
-  // are fetched with scalar loads
-  typedef const __attribute__((address_space(4))) uint32_t* cword_ptr;
-  const cword_ptr crec = (cword_ptr)a.rec;
-  auto load_rec = [&](int sidx) __attribute__((always_inline)) {
-    constexpr int RD = (int)(sizeof(SampleRec<W>) / 4);
-    uint32_t w[RD];
-    const cword_ptr p = crec + (int64_t)sidx * RD;
+  const int fbase = fchunk * 64 * FPL;
+  int fq[FPL];
+  double fcc[FPL];
 #pragma unroll
-    for (int q = 0; q < RD; ++q) w[q] = p[q];
-    SampleRec<W> out;
-    __builtin_memcpy(&out, w, sizeof(out));
-    return out;
-  };
-
-  // runs of base cells: row j (A = j - (W-1)), x in [tx0 - (W-1), tx0 + T)
-  if (lane < NB) {
+  for (int h = 0; h < FPL; ++h) {
+    fq[h] = fbase + 64 * h + lane;
+    fcc[h] = a.fcc[fq[h] < a.nf ? fq[h] : a.nf - 1];
+  }
+  // runs of first-tap cells: row j (y offset j - (W-1)), x in [tx0 - (W-1), tx0 + TX)
+  if (lane < NBY) {
     int cy = ty0 + lane - (W - 1);
     cy = cy < 0 ? cy + a.my : cy;
     const int64_t row = (int64_t)cy * a.mx;
     const int xlo = tx0 - (W - 1);
-    const int xhi = tx0 + T;
+    const int xhi = tx0 + TX;
     int s0, e0, s1 = 0, e1 = 0;
     if (xlo >= 0) {
       s0 = a.cell_start[row + xlo];
@@ -155,97 +157,146 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
     while (seg_off[k + 1] <= t) ++k;
     return seg_s[k] + (t - seg_off[k]);
   };
-  // echo rows of a chunk into LDS with direct global-to-LDS loads
+  // per-sample fields gathered lane-parallel (lane k: the chunk's k-th sample)
+  const SampleRec<W>* __restrict__ grec = (const SampleRec<W>*)a.rec;
+  auto gather_beta = [&](int sidx) __attribute__((always_inline)) -> double {
+    return sidx >= 0 ? grec[sidx].beta : 0.0;
+  };
+  auto gather_idx = [&](int sidx) __attribute__((always_inline)) -> int {
+    if (sidx < 0) return 0;
+    const uint32_t cxy = *(const uint32_t*)&grec[sidx].cx;   // cx low half, cy high half
+    const int aa = ((int)(cxy >> 16) - ty0) & (a.my - 1);    // last-tap row offset in [0, NBY)
+    const int bb = ((int)(cxy & 0xffffu) - tx0) & (a.mx - 1);  // last-tap column offset in [0, NBX)
+    return aa * NBX + bb;
+  };
+  // echo rows of a chunk into LDS with direct global-to-LDS loads; 16-byte
+  // loads need every complex pair (2 frequencies) to lie inside the row
+  const bool quad_ok = (a.nf & 1) == 0;
   auto stage_echo = [&](int c, int srcv) __attribute__((always_inline)) {
     const int n = min(CH, total - c * CH);
     for (int k = 0; k < n; ++k) {
       const int src = __builtin_amdgcn_readlane(srcv, k);
       if constexpr (ET == SAR_ECHO_C64) {
         const float* row = (const float*)a.echo + (int64_t)src * a.nf * 2;
+        if (quad_ok) {
+          // one 16-byte load per lane covers the 128 frequencies (2 per lane)
+          const int fi = fbase * 2 + 4 * lane;
+          dma_quad(row + (fi < 2 * a.nf ? fi : 0), echobuf + k * EB);
+        } else {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int fi = fbase * 2 + h * 64 + lane;   // float index within the row
-          dma_dword(row + (fi < 2 * a.nf ? fi : 0), echobuf + k * EB + h * 256);
+          for (int q = 0; q < 2 * FPL; ++q) {
+            const int fi = fbase * 2 + q * 64 + lane;   // float index within the row
+            dma_dword(row + (fi < 2 * a.nf ? fi : 0), echobuf + k * EB + q * 256);
+          }
         }
       } else {
         const uint32_t* row = (const uint32_t*)a.echo + (int64_t)src * a.nf;
-        const int fi = fbase + lane;
-        dma_dword(row + (fi < a.nf ? fi : 0), echobuf + k * EB);
+#pragma unroll
+        for (int q = 0; q < FPL; ++q) {
+          const int fi = fbase + q * 64 + lane;
+          dma_dword(row + (fi < a.nf ? fi : 0), echobuf + k * EB + q * 256);
+        }
       }
     }
   };
-
-  float2 acc[T][T];
+  // kernel weights of one sample through scalar loads
+  typedef const __attribute__((address_space(4))) float* cfloat_ptr;
+  const cfloat_ptr cw = (cfloat_ptr)a.rec;
+  constexpr int RF = (int)(sizeof(SampleRec<W>) / 4);           // record size in words
+  constexpr int WOFF = (int)(offsetof(SampleRec<W>, wx) / 4);   // first weight word
+  struct Weights {
+    float wx[W], wy[W];
+  };
+  auto load_weights = [&](int sidx) __attribute__((always_inline)) {
+    const cfloat_ptr p = cw + (int64_t)sidx * RF + WOFF;
+    Weights out;
 #pragma unroll
-  for (int r = 0; r < T; ++r)
-#pragma unroll
-    for (int c = 0; c < T; ++c) acc[r][c] = make_float2(0.f, 0.f);
+    for (int q = 0; q < W; ++q) {
+      out.wx[q] = p[q];
+      out.wy[q] = p[W + q];
+    }
+    return out;
+  };
 
-  // pipeline: echo of chunk c+1 and source rows of chunk c+2 are in flight
-  // while chunk c is processed from registers
+  float2 acc[TY][TX][FPL];
+#pragma unroll
+  for (int r = 0; r < TY; ++r)
+#pragma unroll
+    for (int c = 0; c < TX; ++c)
+#pragma unroll
+      for (int h = 0; h < FPL; ++h) acc[r][c][h] = make_float2(0.f, 0.f);
+
+  // pipeline: while chunk c is processed from registers, the echo rows of
+  // chunk c+1, the residual paths and offsets of chunk c+1 and the source rows
+  // of chunk c+2 are in flight
   int sidx0 = chunk_index(0);
   int sidx1 = chunk_index(1);
-  int src0 = sidx0 >= 0 ? a.order[sidx0] : 0;
+  double beta0 = gather_beta(sidx0);
+  int idx0 = gather_idx(sidx0);
   int src1 = sidx1 >= 0 ? a.order[sidx1] : 0;
-  if (nchunk > 0) stage_echo(0, src0);
+  if (nchunk > 0) stage_echo(0, sidx0 >= 0 ? a.order[sidx0] : 0);
+  typedef float evec __attribute__((ext_vector_type(2 * FPL * CH)));
   for (int c = 0; c < nchunk; ++c) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const int n = __builtin_amdgcn_readfirstlane(min(CH, total - c * CH));
-    // the chunk's echo values (re, im interleaved) in one register vector,
-    // indexed below with a uniform sample index
-    typedef float evec __attribute__((ext_vector_type(2 * CH)));
+    // the chunk's compensated values in one register vector: [sample][freq][re, im]
+    // s_hat = s exp(+j 2 pi f beta / c), k * beta in float64 reduced modulo a cycle
     evec ev;
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
-      float2 t2;
-      if constexpr (ET == SAR_ECHO_C64) {
-        t2 = *(const float2*)(echobuf + k * EB + lane * 8);
-      } else {
-        t2 = __half22float2(*(const __half2*)(echobuf + k * EB + lane * 4));
-        t2 = make_float2(t2.x * a.echo_scale, t2.y * a.echo_scale);
+      const double bk = readlane_f64(beta0, k);
+#pragma unroll
+      for (int h = 0; h < FPL; ++h) {
+        float2 t2;
+        if constexpr (ET == SAR_ECHO_C64) {
+          t2 = *(const float2*)(echobuf + k * EB + h * EBH + lane * 8);
+        } else {
+          t2 = __half22float2(*(const __half2*)(echobuf + k * EB + h * EBH + lane * 4));
+          t2 = make_float2(t2.x * a.echo_scale, t2.y * a.echo_scale);
+        }
+        const float2 v = cmul(t2, cis_cycles(bk * fcc[h]));
+        ev[(k * FPL + h) * 2] = v.x;
+        ev[(k * FPL + h) * 2 + 1] = v.y;
       }
-      ev[2 * k] = t2.x;
-      ev[2 * k + 1] = t2.y;
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (c + 1 < nchunk) stage_echo(c + 1, src1);
     const int sidx2 = chunk_index(c + 2);
     const int src2 = sidx2 >= 0 ? a.order[sidx2] : 0;
-    SampleRec<W> r = load_rec(__builtin_amdgcn_readlane(sidx0, 0));
+    const double beta1 = gather_beta(sidx1);
+    const int idx1 = gather_idx(sidx1);
+    Weights wt = load_weights(__builtin_amdgcn_readlane(sidx0, 0));
     for (int k = 0; k < n; ++k) {
-      // consume the current record (its scalar load was issued one sample ago)
-      int A = (int)r.cy - ty0;
-      if (A < -(W - 1)) A += a.my;
-      if (A >= T) A -= a.my;
-      int b = (int)r.cx - tx0;
-      if (b < -(W - 1)) b += a.mx;
-      if (b >= T) b -= a.mx;
-      const int idx = __builtin_amdgcn_readfirstlane((A + (W - 1)) * NB + (b + (W - 1)));
-      const double arg = r.beta * fcc;
-      const SampleRec<W> rc = r;
+      const int idx = __builtin_amdgcn_readlane(idx0, k);
+      const Weights wc = wt;
       // scalar loads return out of order and can only be waited for all
-      // together: issue the next record's load only after the current one
+      // together: issue the next sample's load only after the current one
       // has been consumed
       asm volatile("" ::: "memory");
-      if (k + 1 < n) r = load_rec(__builtin_amdgcn_readlane(sidx0, k + 1));
-      const float2 e = make_float2(ev[2 * k], ev[2 * k + 1]);
-      // compensation: s_hat = s exp(+j 2 pi f beta / c)
-      const float2 v = cmul(e, cis_cycles(arg));
-      dispatch_range<0, NB * NB>(idx, [&](auto ic) __attribute__((always_inline)) {
+      if (k + 1 < n) wt = load_weights(__builtin_amdgcn_readlane(sidx0, k + 1));
+      float2 v[FPL];
+#pragma unroll
+      for (int h = 0; h < FPL; ++h) v[h] = make_float2(ev[(k * FPL + h) * 2], ev[(k * FPL + h) * 2 + 1]);
+      dispatch_range<0, NBY * NBX>(idx, [&](auto ic) __attribute__((always_inline)) {
         constexpr int I = decltype(ic)::value;
-        constexpr int AA = I / NB - (W - 1);
-        constexpr int BB = I % NB - (W - 1);
+        constexpr int AA = I / NBX - (W - 1);   // first-tap row offset
+        constexpr int BB = I % NBX - (W - 1);   // first-tap column offset
         static_for<0, W>([&](auto jc) __attribute__((always_inline)) {
           constexpr int jj = decltype(jc)::value;
           constexpr int rr = AA + jj;
-          if constexpr (rr >= 0 && rr < T) {
-            const float2 vy = cscale(v, rc.wy[jj]);
+          if constexpr (rr >= 0 && rr < TY) {
+            float2 vy[FPL];
+#pragma unroll
+            for (int h = 0; h < FPL; ++h) vy[h] = cscale(v[h], wc.wy[jj]);
             static_for<0, W>([&](auto kc) __attribute__((always_inline)) {
               constexpr int kk = decltype(kc)::value;
               constexpr int cc = BB + kk;
-              if constexpr (cc >= 0 && cc < T) cfma(acc[rr][cc], vy, rc.wx[kk]);
+              if constexpr (cc >= 0 && cc < TX) {
+#pragma unroll
+                for (int h = 0; h < FPL; ++h) cfma(acc[rr][cc][h], vy[h], wc.wx[kk]);
+              }
             });
           }
         });
@@ -254,14 +305,19 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
     sidx0 = sidx1;
     sidx1 = sidx2;
     src1 = src2;
+    beta0 = beta1;
+    idx0 = idx1;
   }
 
-  if (active) {
 #pragma unroll
-    for (int r = 0; r < T; ++r)
+  for (int h = 0; h < FPL; ++h) {
+    if (fq[h] < a.nf) {
 #pragma unroll
-      for (int c = 0; c < T; ++c)
-        a.grid[((int64_t)(ty0 + r) * a.mx + (tx0 + c)) * a.nf + f] = acc[r][c];
+      for (int r = 0; r < TY; ++r)
+#pragma unroll
+        for (int c = 0; c < TX; ++c)
+          a.grid[((int64_t)(ty0 + r) * a.mx + (tx0 + c)) * a.nf + fq[h]] = acc[r][c][h];
+    }
   }
 }
 
@@ -279,9 +335,9 @@ sar_status grid_w(const Plan& p, const void* d_echo, float echo_scale, const Wor
   a.mx = p.mx;
   a.my = p.my;
   a.nf = p.nf;
-  a.ntx = p.mx / T;
-  a.nty = p.my / T;
-  const int nfc = (p.nf + 63) / 64;
+  a.ntx = p.mx / TX;
+  a.nty = p.my / TY;
+  const int nfc = (p.nf + 64 * FPL - 1) / (64 * FPL);
   const int64_t nblk = (int64_t)a.ntx * a.nty * nfc;
   if (p.echo_type == SAR_ECHO_C64)
     k_grid<W, SAR_ECHO_C64><<<(unsigned)nblk, 64, 0, stream>>>(a);

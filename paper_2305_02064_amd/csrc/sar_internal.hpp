@@ -6,21 +6,22 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sar.h"
+#include "sar.h"
 
 namespace sar {
 
 constexpr int kNumStages = 7;
-constexpr int kTile = 8;        // gridding tile edge (cells)
+constexpr int kTileX = 8;       // gridding tile: cells along x
+constexpr int kTileY = 4;       // gridding tile: cells along y
 constexpr int kMaxWidth = 8;    // largest lateral kernel width
 
 // Geometry of one virtual-sample record in the sorted list consumed by the
-// gridding kernel: source row of the echo, base cell (first tap), residual
+// gridding kernel: source row of the echo, cell of the last tap, residual
 // path and the separable kernel weights of its W taps along x and y.
 template <int W>
 struct alignas(16) SampleRec {
   int32_t src;     // shot * n_pair + pair
-  int16_t cx, cy;  // base cell (first tap), 0 <= cx < mx, 0 <= cy < my
+  int16_t cx, cy;  // cell of the last tap: (first-tap cell + W - 1) mod (mx, my)
   double beta;     // residual path (m)
   float wx[W];
   float wy[W];
