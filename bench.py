@@ -1,6 +1,7 @@
 """Benchmark of the per-scan image formation on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --copy-calibration BYTES
 
 Workload: one large freehand scan -- 2Tx x 4Rx array, 256 frequencies over
 77-81 GHz, 512 x 256 shots along a smooth seeded random-walk trajectory
@@ -8,6 +9,10 @@ Workload: one large freehand scan -- 2Tx x 4Rx array, 256 frequencies over
 is one sar_reconstruct call: geometry + sort, compensation + gridding, 2-D
 FFT, k_z filter + Stolt, inverse 2-D FFT, with inputs already resident in
 HBM.  Prints one JSON line.
+
+--copy-calibration runs only a plain device copy (y = -x over float32) of
+BYTES bytes, three times: the reference for scaling the HBM byte counters
+(FETCH_SIZE, WRITE_SIZE) of a profiled run to bytes.
 """
 
 import argparse
@@ -96,6 +101,18 @@ def cpu_baseline(scan, echo_host_fn):
     }
 
 
+def copy_calibration(nbytes, launches=3):
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(launches):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": x.numel() * 4, "bytes_written": y.numel() * 4,
+                                           "launches": launches}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,11 +120,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build runs on a single MI355X); got --gpus {args.gpus}",
+        print(f"bench.py measures one GPU only: the library forms each image on a single device (got --gpus {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import numpy as np
     import torch

@@ -24,8 +24,11 @@ __global__ __launch_bounds__((L1 > L2 ? L1 : L2) * BC) void k_fft_lines(FftLines
   constexpr int RS = (L2 + 1) * BC;  // padded LDS row (one l1) to spread banks
   extern __shared__ float2 lds[];     // [L1][L2 + 1][BC]
   const int64_t nbc = (a.B + BC - 1) / BC;
-  const int64_t o = blockIdx.x / nbc;
-  const int64_t bc = blockIdx.x - o * nbc;
+  // consecutive column groups share cache lines when BC * 8 < 128 bytes: the
+  // remap runs them back to back on one XCD so the second finds them in L2
+  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t o = bid / nbc;
+  const int64_t bc = bid - o * nbc;
   const int b = threadIdx.x % BC;
   const int t = threadIdx.x / BC;
   const int64_t bg = bc * BC + b;
@@ -81,14 +84,12 @@ sar_status launch_lb(const FftLines& a, hipStream_t stream) {
   const int64_t nblk = nbc * a.n_outer;
   if (nblk <= 0) return SAR_OK;
   if (nblk > 0x7fffffffLL) return fail(SAR_ERR_UNSUPPORTED, "FFT batch too large");
-  static bool attr_set = false;
-  if (!attr_set) {
-    // blocks may use more than the default 64 KiB of dynamic LDS
-    (void)hipFuncSetAttribute((const void*)k_fft_lines<L1, L2, BC, -1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-    (void)hipFuncSetAttribute((const void*)k_fft_lines<L1, L2, BC, +1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-    attr_set = true;
+  // blocks may use more than the default 64 KiB of dynamic LDS; the attribute
+  // is set on every launch so it holds on whichever device is current
+  const void* fn = a.sign < 0 ? (const void*)k_fft_lines<L1, L2, BC, -1> : (const void*)k_fft_lines<L1, L2, BC, +1>;
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return check_hip(e, "fft LDS attribute");
   }
   if (a.sign < 0)
     k_fft_lines<L1, L2, BC, -1><<<(unsigned)nblk, NT, lds, stream>>>(a);

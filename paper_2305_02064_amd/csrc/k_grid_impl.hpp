@@ -35,6 +35,13 @@
 #include "device_common.hpp"
 #include "sar_internal.hpp"
 
+// Repeats M(I) for I = 0 .. 191 (covers NBY * NBX up to (4 + 7) * (8 + 7) = 165).
+#define SAR_GRID_R4(M, B) M((B)) M((B) + 1) M((B) + 2) M((B) + 3)
+#define SAR_GRID_R16(M, B) SAR_GRID_R4(M, B) SAR_GRID_R4(M, (B) + 4) SAR_GRID_R4(M, (B) + 8) SAR_GRID_R4(M, (B) + 12)
+#define SAR_GRID_R64(M, B) \
+  SAR_GRID_R16(M, B) SAR_GRID_R16(M, (B) + 16) SAR_GRID_R16(M, (B) + 32) SAR_GRID_R16(M, (B) + 48)
+#define SAR_GRID_CASES(M) SAR_GRID_R64(M, 0) SAR_GRID_R64(M, 64) SAR_GRID_R64(M, 128)
+
 namespace sar {
 namespace grid_impl {
 
@@ -53,19 +60,6 @@ struct GridArgs {
   int mx, my, nf;
   int ntx, nty;
 };
-
-template <int LO, int HI, typename F>
-__device__ __forceinline__ void dispatch_range(int idx, F&& f) {
-  if constexpr (HI - LO == 1) {
-    f(std::integral_constant<int, LO>{});
-  } else {
-    constexpr int MID = (LO + HI) / 2;
-    if (idx < MID)
-      dispatch_range<LO, MID>(idx, f);
-    else
-      dispatch_range<MID, HI>(idx, f);
-  }
-}
 
 // value of lane k of a float64 register pair
 __device__ __forceinline__ double readlane_f64(double v, int k) {
@@ -92,6 +86,7 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
   constexpr int CH = 8;               // samples per pipeline chunk
   constexpr int EBH = ET == SAR_ECHO_C64 ? 512 : 256;  // echo bytes per sample, per 64 frequencies
   constexpr int EB = FPL * EBH;
+  static_assert(NBY * NBX <= 192, "pattern chain covers 192 patterns");
   __shared__ int seg_s[NSEG];
   __shared__ int seg_off[NSEG + 1];
   __shared__ __attribute__((aligned(16))) char echobuf[CH * EB];
@@ -268,8 +263,13 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
     const double beta1 = gather_beta(sidx1);
     const int idx1 = gather_idx(sidx1);
     Weights wt = load_weights(__builtin_amdgcn_readlane(sidx0, 0));
-    for (int k = 0; k < n; ++k) {
-      const int idx = __builtin_amdgcn_readlane(idx0, k);
+    // one sample with its tap pattern fixed at compile time: I = row offset *
+    // NBX + column offset of its last tap relative to the tile
+    int k = 0;
+    auto visit = [&](auto ic) __attribute__((always_inline)) {
+      constexpr int I = decltype(ic)::value;
+      constexpr int AA = I / NBX - (W - 1);   // first-tap row offset
+      constexpr int BB = I % NBX - (W - 1);   // first-tap column offset
       const Weights wc = wt;
       // scalar loads return out of order and can only be waited for all
       // together: issue the next sample's load only after the current one
@@ -279,29 +279,56 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
       float2 v[FPL];
 #pragma unroll
       for (int h = 0; h < FPL; ++h) v[h] = make_float2(ev[(k * FPL + h) * 2], ev[(k * FPL + h) * 2 + 1]);
-      dispatch_range<0, NBY * NBX>(idx, [&](auto ic) __attribute__((always_inline)) {
-        constexpr int I = decltype(ic)::value;
-        constexpr int AA = I / NBX - (W - 1);   // first-tap row offset
-        constexpr int BB = I % NBX - (W - 1);   // first-tap column offset
-        static_for<0, W>([&](auto jc) __attribute__((always_inline)) {
-          constexpr int jj = decltype(jc)::value;
-          constexpr int rr = AA + jj;
-          if constexpr (rr >= 0 && rr < TY) {
-            float2 vy[FPL];
+      static_for<0, W>([&](auto jc) __attribute__((always_inline)) {
+        constexpr int jj = decltype(jc)::value;
+        constexpr int rr = AA + jj;
+        if constexpr (rr >= 0 && rr < TY) {
+          float2 vy[FPL];
 #pragma unroll
-            for (int h = 0; h < FPL; ++h) vy[h] = cscale(v[h], wc.wy[jj]);
-            static_for<0, W>([&](auto kc) __attribute__((always_inline)) {
-              constexpr int kk = decltype(kc)::value;
-              constexpr int cc = BB + kk;
-              if constexpr (cc >= 0 && cc < TX) {
+          for (int h = 0; h < FPL; ++h) vy[h] = cscale(v[h], wc.wy[jj]);
+          static_for<0, W>([&](auto kc) __attribute__((always_inline)) {
+            constexpr int kk = decltype(kc)::value;
+            constexpr int cc = BB + kk;
+            if constexpr (cc >= 0 && cc < TX) {
 #pragma unroll
-                for (int h = 0; h < FPL; ++h) cfma(acc[rr][cc][h], vy[h], wc.wx[kk]);
-              }
-            });
-          }
-        });
+              for (int h = 0; h < FPL; ++h) cfma(acc[rr][cc][h], vy[h], wc.wx[kk]);
+            }
+          });
+        }
       });
+    };
+    // The sorted list walks the tile's cells in increasing pattern index, so
+    // the chunk enters the chain of patterns once, at its first sample's
+    // pattern, and falls through the later ones in order: per sample only one
+    // compare and the loop branch remain.  A sample whose pattern lies behind
+    // the chain's position re-enters it, and an index outside the chain (not
+    // produced by the record kernel) is skipped, so every sample is visited
+    // at most once and the loop always ends.
+    int cur = __builtin_amdgcn_readlane(idx0, 0);
+    for (;;) {
+      switch (cur) {
+#define SAR_GRID_CASE(I)                                                   \
+  case (I):                                                                \
+    if constexpr ((I) < NBY * NBX) {                                       \
+      while (cur == (I)) {                                                 \
+        visit(std::integral_constant<int, (I)>{});                         \
+        if (++k >= n) goto chunk_done;                                     \
+        cur = __builtin_amdgcn_readlane(idx0, k);                          \
+      }                                                                    \
+    }                                                                      \
+    [[fallthrough]];
+        SAR_GRID_CASES(SAR_GRID_CASE)
+#undef SAR_GRID_CASE
+        default:
+          break;
+      }
+      if (cur < 0 || cur >= NBY * NBX) {
+        if (++k >= n) break;
+        cur = __builtin_amdgcn_readlane(idx0, k);
+        wt = load_weights(__builtin_amdgcn_readlane(sidx0, k));
+      }
     }
+  chunk_done:
     sidx0 = sidx1;
     sidx1 = sidx2;
     src1 = src2;
