@@ -57,6 +57,7 @@ extern "C" {
 #endif
 
 typedef struct sar_plan_s* sar_plan;
+typedef struct sar_server_s* sar_server;
 typedef void* sar_stream_t; /* a hipStream_t */
 
 typedef enum {
@@ -170,6 +171,47 @@ sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* 
  * the records.  ms must hold sar_plan_info.n_stages doubles. */
 sar_status sar_plan_set_timing(sar_plan plan, int enable);
 sar_status sar_plan_stage_times(sar_plan plan, double* ms, int32_t n, int64_t* n_calls);
+
+/* ---- Serving: continuous admission of scans under a device-memory budget ----
+ * The paper forms one image per scan (Sec. III); a server runs that same
+ * per-scan pipeline for a stream of independent scans of different sizes,
+ * overlapping them on one device.
+ *
+ * sar_server_create: a server on HIP device `device` owning one arena of
+ *   hbm_budget_bytes of device memory (rounded down to 256 bytes), four HIP
+ *   streams and a worker thread.  Errors: SAR_ERR_INVALID (no such device,
+ *   budget < 256 bytes), SAR_ERR_NOMEM (arena allocation failed).
+ *
+ * sar_submit: queue one scan; returns at once with a ticket.
+ *   plan           a plan created on the server's device; it must outlive the request
+ *   pos_xyz, echo  positions [n_pos][3] (double) and echo [n_pos][n_pair][n_freq]
+ *                  of the plan's echo type: device memory if echo_on_device != 0,
+ *                  else host memory (pinned for full copy speed) that the server
+ *                  uploads into its arena on the scan's stream
+ *   image_dst      device float2 [nx][ny][nz], written
+ *   The caller must keep every buffer unchanged until sar_poll reports the
+ *   ticket done.  Requests are admitted in arrival order as soon as their
+ *   memory (sar_plan_workspace_bytes, plus the uploaded inputs for host
+ *   inputs) fits in the arena and fewer than eight scans are in flight;
+ *   admitted scans run concurrently on the least-loaded stream.
+ *   Errors: SAR_ERR_INVALID (arguments, plan on another device),
+ *   SAR_ERR_NOMEM (the request alone exceeds the whole budget; a request
+ *   that merely does not fit yet waits), SAR_ERR_BUSY (server shutting down).
+ *
+ * sar_poll: non-blocking.  *done = 0 while the scan is queued or running.
+ *   When it has finished, *done = 1, *latency_s (if not NULL) = seconds from
+ *   sar_submit to the completion of the scan's last kernel, the ticket is
+ *   released (a later poll of it gives SAR_ERR_NOT_FOUND), and the return
+ *   value is the scan's own status (SAR_OK, or the error it failed with,
+ *   described by sar_last_error()).
+ *
+ * sar_server_destroy: waits until every submitted scan has finished, then
+ *   releases the arena, streams and thread.  NULL is accepted. */
+sar_status sar_server_create(int device, size_t hbm_budget_bytes, sar_server* out);
+sar_status sar_submit(sar_server server, sar_plan plan, const double* pos_xyz, int64_t n_pos, const void* echo,
+                      int echo_on_device, float echo_scale, void* image_dst, uint64_t* ticket);
+sar_status sar_poll(sar_server server, uint64_t ticket, int* done, double* latency_s);
+sar_status sar_server_destroy(sar_server server);
 
 /* Thread-local description of the last failure on this thread. */
 const char* sar_last_error(void);

@@ -19,7 +19,7 @@ OUT = os.path.join(PKG, "libsar.so")
 BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["k_grid_w8.hip", "k_grid_w7.hip", "k_grid_w6.hip", "k_grid_w5.hip", "k_grid_w4.hip", "k_grid_w3.hip",
-           "k_fft.hip", "k_stolt.hip", "k_geometry.hip", "k_grid.cpp", "plan.cpp", "api.cpp"]
+           "k_fft.hip", "k_stolt.hip", "k_geometry.hip", "k_grid.cpp", "plan.cpp", "api.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -36,10 +36,10 @@ def _compile(src):
     lang = ["-x", "hip"]
     extra = []
     if src.startswith("k_grid_w"):
-        # keep the unrolled per-offset bodies of the gridding dispatch as
-        # separate uniform branches: no sinking into a pointer phi (which would
+        # keep the unrolled per-pattern bodies of the gridding chain as
+        # separate uniform blocks: no sinking into a pointer phi (which would
         # push the accumulator tile to scratch memory) and no structurisation of
-        # the uniform branch tree (which would add register copies on every path)
+        # the uniform control flow (which would add register copies on every path)
         extra = ["-mllvm", "-simplifycfg-sink-common=false",
                  "-mllvm", "-structurizecfg-skip-uniform-regions=true"]
     cmd = [HIPCC] + COMMON + extra + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
@@ -55,7 +55,7 @@ def build(jobs=None, verbose=False):
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

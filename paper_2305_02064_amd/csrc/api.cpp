@@ -158,17 +158,35 @@ sar_status run_back(Plan& p, const float2* spec, void* d_image, const Workspace&
 
 sar_status check_call(sar_plan plan, int64_t n_pos, const void* d_pos, const void* d_echo, const void* d_out,
                       const void* d_ws) {
-  if (!plan) return fail(SAR_ERR_INVALID, "plan is NULL");
-  const Plan& p = plan->p;
-  if (n_pos < 0 || n_pos > p.max_pos) return fail(SAR_ERR_INVALID, "n_pos outside [0, max_pos]");
-  if (n_pos > 0 && (!d_pos || !d_echo)) return fail(SAR_ERR_INVALID, "positions or echo pointer is NULL");
-  if (!d_out) return fail(SAR_ERR_INVALID, "output pointer is NULL");
+  sar_status st = check_reconstruct_args(plan, n_pos, d_pos, d_echo, d_out);
+  if (st != SAR_OK) return st;
   if (!d_ws) return fail(SAR_ERR_INVALID, "workspace pointer is NULL");
   if (!aligned256(d_ws)) return fail(SAR_ERR_INVALID, "workspace must be 256-byte aligned");
   return SAR_OK;
 }
 
 }  // namespace
+
+sar_status reconstruct_on(Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
+                          void* d_image, void* d_workspace, hipStream_t stream) {
+  Workspace ws;
+  workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
+  Timer tm(p, stream, false);
+  sar_status st = run_front(p, d_pos, n_pos, d_echo, echo_scale, ws.region_a, ws, stream, tm);
+  if (st != SAR_OK) return st;
+  return run_back(p, ws.region_a, d_image, ws, stream, tm, 4);
+}
+
+sar_status check_reconstruct_args(sar_plan plan, int64_t n_pos, const void* pos, const void* echo,
+                                  const void* image) {
+  if (!plan) return fail(SAR_ERR_INVALID, "plan is NULL");
+  const Plan& p = plan->p;
+  if (n_pos < 0 || n_pos > p.max_pos) return fail(SAR_ERR_INVALID, "n_pos outside [0, max_pos]");
+  if (n_pos > 0 && (!pos || !echo)) return fail(SAR_ERR_INVALID, "positions or echo pointer is NULL");
+  if (!image) return fail(SAR_ERR_INVALID, "output pointer is NULL");
+  return SAR_OK;
+}
+
 }  // namespace sar
 
 using namespace sar;

@@ -108,6 +108,13 @@ struct FftLines {
 sar_status launch_fft_lines(const FftLines& a, hipStream_t stream);
 sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, hipStream_t stream);
 
+// whole per-scan pipeline on `stream` without stage timing (used by the server)
+sar_status reconstruct_on(Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
+                          void* d_image, void* d_workspace, hipStream_t stream);
+// argument checks shared by sar_reconstruct and sar_submit (sets the error text)
+sar_status check_reconstruct_args(sar_plan plan, int64_t n_pos, const void* pos, const void* echo,
+                                  const void* image);
+
 }  // namespace sar
 
 struct sar_plan_s {

@@ -91,6 +91,10 @@ def library():
         "sar_image_from_spectrum": ([vp, vp, vp, vp, vp], i32),
         "sar_plan_set_timing": ([vp, ctypes.c_int], i32),
         "sar_plan_stage_times": ([vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i64)], i32),
+        "sar_server_create": ([ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)], i32),
+        "sar_submit": ([vp, vp, vp, i64, vp, ctypes.c_int, f32, vp, ctypes.POINTER(ctypes.c_uint64)], i32),
+        "sar_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)], i32),
+        "sar_server_destroy": ([vp], i32),
         "sar_last_error": ([], ctypes.c_char_p),
         "sar_version": ([], ctypes.c_char_p),
     }
@@ -207,10 +211,103 @@ def sar_plan_stage_times(plan):
     return dict(zip(STAGES, list(ms))), int(n.value)
 
 
-class Plan:
-    """Owns a plan handle plus a device workspace sized for max_pos shots."""
+def _ptr(t, name, dtype=None):
+    """Raw pointer of a contiguous host or device tensor."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
 
-    def __init__(self, tx_xy, rx_xy, freq_hz, grid, max_pos, device=0, **kw):
+
+def sar_server_create(device, hbm_budget_bytes):
+    h = ctypes.c_void_p()
+    _check(library().sar_server_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
+    return h
+
+
+def sar_submit(server, plan, pos, n_pos, echo, echo_scale, image):
+    """Queue one scan; pos and echo are both device tensors or both host tensors."""
+    if pos.is_cuda != echo.is_cuda:
+        raise ValueError("pos and echo must both be on the device or both on the host")
+    t = ctypes.c_uint64()
+    _check(library().sar_submit(server, plan, _ptr(pos, "pos", torch.float64), int(n_pos), _ptr(echo, "echo"),
+                                1 if echo.is_cuda else 0, float(echo_scale),
+                                _dptr(image, "image", torch.complex64), ctypes.byref(t)))
+    return int(t.value)
+
+
+def sar_poll(server, ticket):
+    """(done, latency_s); raises SarError if the scan failed."""
+    done = ctypes.c_int()
+    lat = ctypes.c_double()
+    _check(library().sar_poll(server, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(lat)))
+    return bool(done.value), (float(lat.value) if done.value else None)
+
+
+def sar_server_destroy(server):
+    _check(library().sar_server_destroy(server))
+
+
+class Server:
+    """A serving loop (sar_server_*): scans are submitted, overlap on the
+    device under an HBM budget, and are collected by polling.  The buffers of
+    a submitted scan are kept referenced here until it is collected."""
+
+    def __init__(self, hbm_budget_bytes, device=0):
+        self.device = torch.device("cuda", device)
+        self.handle = sar_server_create(device, hbm_budget_bytes)
+        self._held = {}
+
+    def submit(self, plan, pos, echo, image=None, echo_scale=1.0):
+        image = plan.new_image() if image is None else image
+        ticket = sar_submit(self.handle, plan.handle, pos, pos.shape[0], echo, echo_scale, image)
+        self._held[ticket] = (pos, echo, image)
+        return ticket
+
+    def poll(self, ticket):
+        """(done, latency_s, image); image is None until done."""
+        try:
+            done, lat = sar_poll(self.handle, ticket)
+        except SarError:
+            self._held.pop(ticket, None)
+            raise
+        if not done:
+            return False, None, None
+        return True, lat, self._held.pop(ticket)[2]
+
+    def wait(self, ticket, timeout=60.0, spin=50e-6):
+        """Poll until the scan is done; returns (latency_s, image)."""
+        import time
+        t_end = time.perf_counter() + timeout
+        while True:
+            done, lat, img = self.poll(ticket)
+            if done:
+                return lat, img
+            if time.perf_counter() > t_end:
+                raise TimeoutError(f"scan {ticket} not done after {timeout} s")
+            time.sleep(spin)
+
+    def close(self):
+        if self.handle is not None:
+            sar_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Owns a plan handle plus (unless workspace=False) a device workspace
+    sized for max_pos shots."""
+
+    def __init__(self, tx_xy, rx_xy, freq_hz, grid, max_pos, device=0, workspace=True, **kw):
         self.grid = grid
         self.device = torch.device("cuda", device)
         self.n_pair = len(tx_xy) * len(rx_xy)
@@ -220,10 +317,12 @@ class Plan:
                                       device=device, **kw)
         self.info = sar_plan_get_info(self.handle)
         self.max_pos = max_pos
-        nbytes = max(self.info["workspace_bytes_max"], 256)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        off = (-self.workspace.data_ptr()) % 256
-        self.ws = self.workspace[off:off + nbytes]
+        self.workspace = self.ws = None
+        if workspace:
+            nbytes = max(self.info["workspace_bytes_max"], 256)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.workspace.data_ptr()) % 256
+            self.ws = self.workspace[off:off + nbytes]
 
     def new_image(self):
         g = self.grid

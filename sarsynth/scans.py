@@ -296,16 +296,17 @@ def _snap_235(s: int, lo: int = 64, hi: int = 256) -> int:
     return min(cands, key=lambda v: (abs(v - s), v))
 
 
-def config4_scan(seed: int, with_echo: bool = True, device=None, pow2: bool = False) -> Scan:
+def config4_scan(seed: int, with_echo: bool = True, device=None) -> Scan:
     """One scan of the uneven batch: side s log-uniform in [64, 256] snapped to
-    an FFT-friendly size, s x s positions at lambda/4, N_f in {64, 128, 256},
+    a 2^a 3^b 5^c size, s x s positions at lambda/4, N_f in {64, 128, 256},
     smooth z deviation scaled to max |d_z| = A ~ U(1, 2) cm, 20-100 points at
-    z in [0.2, 0.5] m, image s x s x N_f over z in [0.2, 0.5)."""
+    z in [0.2, 0.5] m.  The image covers the aperture: S x S x N_f voxels at
+    lambda/4 laterally with S the power of two at or above s (the library's
+    lateral transforms are power-of-two), z in [0.2, 0.5)."""
     rng = _rng(4, seed)
     lam = LAMBDA_C
     pitch = lam / 4
-    s = int(round(2 ** rng.uniform(6, 8)))
-    s = 1 << int(round(np.log2(s))) if pow2 else _snap_235(s)
+    s = _snap_235(int(round(2 ** rng.uniform(6, 8))))
     nf = int(rng.choice([64, 128, 256]))
     tx, rx = awr1443_layout()
     freq = sweep(nf)
@@ -324,7 +325,8 @@ def config4_scan(seed: int, with_echo: bool = True, device=None, pow2: bool = Fa
     tgt = np.stack([rng.uniform(-0.4 * ext, 0.4 * ext, nt), rng.uniform(-0.4 * ext, 0.4 * ext, nt),
                     rng.uniform(0.2, 0.5, nt)], axis=1)
     amp = (rng.standard_normal(nt) + 1j * rng.standard_normal(nt)) / np.sqrt(2)
-    grid = ImageGrid(nx=s, ny=s, nz=nf, x0=-(s // 2) * pitch, y0=-(s // 2) * pitch, z0=0.2,
+    side = 1 << int(np.ceil(np.log2(s)))
+    grid = ImageGrid(nx=side, ny=side, nz=nf, x0=-(side // 2) * pitch, y0=-(side // 2) * pitch, z0=0.2,
                      dx=pitch, dy=pitch, dz=0.3 / nf, z_ref=0.0, z_focus=0.35)
     scan = Scan(pos=pos, tx_xy=tx, rx_xy=rx, freq=freq, grid=grid, targets=tgt, amps=amp,
                 meta={"config": f"batched-{s}x{s}x{nf}", "seed": seed})

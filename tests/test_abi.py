@@ -82,3 +82,18 @@ def test_null_arguments():
     assert lib.sar_reconstruct(None, None, 0, None, 1.0, None, None, None) == sar.SAR_ERR_INVALID
     assert lib.sar_plan_create(None, 0, None) == sar.SAR_ERR_INVALID
     assert lib.sar_plan_destroy(None) == sar.SAR_OK
+
+
+def test_server_null_and_budget_arguments():
+    # argument checks that return before any device call
+    sar = _sar()
+    lib = sar.library()
+    h = ctypes.c_void_p()
+    assert lib.sar_server_create(0, 1 << 20, None) == sar.SAR_ERR_INVALID
+    assert lib.sar_server_create(0, 16, ctypes.byref(h)) == sar.SAR_ERR_INVALID
+    assert "budget" in sar.sar_last_error()
+    t = ctypes.c_uint64()
+    assert lib.sar_submit(None, None, None, 0, None, 1, 1.0, None, ctypes.byref(t)) == sar.SAR_ERR_INVALID
+    done = ctypes.c_int()
+    assert lib.sar_poll(None, 1, ctypes.byref(done), None) == sar.SAR_ERR_INVALID
+    assert lib.sar_server_destroy(None) == sar.SAR_OK

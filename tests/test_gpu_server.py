@@ -1,0 +1,202 @@
+"""GPU tests of the serving loop (sar_server_* through the C ABI).
+
+Each scan's image from the server, where it runs concurrently with scans of
+other sizes, must equal the image of the plain per-scan call on the same
+inputs (the kernels are deterministic per scan, so the bar is relative L2
+<= 1e-6, far inside the method's 1e-3), and a served tiny scan must match the
+FP64 oracle like the plain path does.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from sarsynth import config1_scan, config4_scan
+from tests.sar_testutil import make_plan, peak_ok, rel_l2, to_device
+
+pytestmark = pytest.mark.gpu
+
+SAME_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _small_mix(torch, n, max_side=128, max_nf=128):
+    """n scans of the uneven batch with image side <= max_side and N_f <=
+    max_nf, seeded random echoes on the device (the server is compared with
+    the plain path, not with the scene)."""
+    from paper_2305_02064_amd import sar
+    out = []
+    seed = 0
+    while len(out) < n:
+        sc = config4_scan(seed, with_echo=False)
+        seed += 1
+        if sc.grid.nx > max_side or sc.n_freq > max_nf:
+            continue
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1000 + seed)
+        shape = (sc.n_pos, sc.n_pair, sc.n_freq)
+        echo = torch.complex(torch.randn(shape, generator=g, device="cuda"),
+                             torch.randn(shape, generator=g, device="cuda"))
+        pos = torch.from_numpy(np.ascontiguousarray(sc.pos)).cuda()
+        plan = sar.Plan(sc.tx_xy, sc.rx_xy, sc.freq, sc.grid, sc.n_pos)
+        out.append((sc, plan, pos, echo))
+    return out
+
+
+@pytest.fixture(scope="module")
+def mix(torch_cuda):
+    scans = _small_mix(torch_cuda, 6)
+    refs = [plan.reconstruct(pos, echo) for _, plan, pos, echo in scans]
+    torch_cuda.cuda.synchronize()
+    return scans, refs
+
+
+def _collect(srv, tickets):
+    out = {}
+    for t in tickets:
+        lat, img = srv.wait(t)
+        assert lat > 0
+        out[t] = img
+    return out
+
+
+def test_same_alone_and_in_the_mix(torch_cuda, mix):
+    from paper_2305_02064_amd import sar
+    scans, refs = mix
+    srv = sar.Server(8 << 30)
+    try:
+        # every scan three times, interleaved, so sizes overlap on the device
+        order = [i for _ in range(3) for i in range(len(scans))]
+        tickets = [(i, srv.submit(scans[i][1], scans[i][2], scans[i][3])) for i in order]
+        imgs = _collect(srv, [t for _, t in tickets])
+    finally:
+        srv.close()
+    exact = 0
+    for i, t in tickets:
+        err = rel_l2(imgs[t].cpu().numpy(), refs[i].cpu().numpy())
+        exact += int(torch_cuda.equal(imgs[t], refs[i]))
+        assert err <= SAME_TOL, (i, err)
+    print(f"{len(tickets)} served scans equal their plain images ({exact} bit-identical)")
+
+
+def test_budget_queues_instead_of_failing(torch_cuda, mix):
+    # a budget that holds about one scan at a time: later scans wait for memory
+    from paper_2305_02064_amd import sar
+    scans, refs = mix
+    need = max(sar.sar_plan_workspace_bytes(plan.handle, sc.n_pos) for sc, plan, _, _ in scans)
+    srv = sar.Server(int(need * 1.5))
+    try:
+        tickets = [(i, srv.submit(scans[i][1], scans[i][2], scans[i][3])) for i in range(len(scans))]
+        imgs = _collect(srv, [t for _, t in tickets])
+    finally:
+        srv.close()
+    for i, t in tickets:
+        assert rel_l2(imgs[t].cpu().numpy(), refs[i].cpu().numpy()) <= SAME_TOL
+
+
+def test_request_larger_than_budget_is_rejected(torch_cuda, mix):
+    from paper_2305_02064_amd import sar
+    scans, _ = mix
+    sc, plan, pos, echo = scans[0]
+    srv = sar.Server(1 << 20)
+    try:
+        with pytest.raises(sar.SarError) as ei:
+            srv.submit(plan, pos, echo)
+        assert ei.value.status == sar.SAR_ERR_NOMEM
+        assert "budget" in str(ei.value)
+    finally:
+        srv.close()
+
+
+def test_host_inputs_are_uploaded(torch_cuda, mix):
+    # echo and positions in pinned host memory: the server stages them in its arena
+    from paper_2305_02064_amd import sar
+    scans, refs = mix
+    srv = sar.Server(4 << 30)
+    try:
+        tickets = []
+        for i in range(3):
+            sc, plan, pos, echo = scans[i]
+            pos_h = pos.cpu().pin_memory()
+            echo_h = echo.cpu().pin_memory()
+            tickets.append((i, srv.submit(plan, pos_h, echo_h)))
+        imgs = _collect(srv, [t for _, t in tickets])
+    finally:
+        srv.close()
+    for i, t in tickets:
+        assert rel_l2(imgs[t].cpu().numpy(), refs[i].cpu().numpy()) <= SAME_TOL
+
+
+def test_served_scan_matches_oracle(torch_cuda):
+    from paper_2305_02064_amd import sar
+    scan = config1_scan(0)
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, scan.grid)
+    plan = make_plan(scan)
+    pos, echo, _ = to_device(scan)
+    srv = sar.Server(1 << 30)
+    try:
+        lat, img = srv.wait(srv.submit(plan, pos, echo))
+    finally:
+        srv.close()
+    img = img.cpu().numpy()
+    err = rel_l2(img, ref)
+    print(f"served tiny scan rel-L2 {err:.3e}, latency {lat * 1e3:.2f} ms")
+    assert err <= 1e-3
+    assert peak_ok(img, ref)
+
+
+def test_half_echo_through_server(torch_cuda):
+    from paper_2305_02064_amd import sar
+    scan = config1_scan(0)
+    plan = make_plan(scan, echo_type=sar.SAR_ECHO_F16X2)
+    pos, eh, scale = to_device(scan, half=True)
+    ref = plan.reconstruct(pos, eh, echo_scale=scale)
+    srv = sar.Server(1 << 30)
+    try:
+        _, img = srv.wait(srv.submit(plan, pos, eh, echo_scale=scale))
+    finally:
+        srv.close()
+    assert rel_l2(img.cpu().numpy(), ref.cpu().numpy()) <= SAME_TOL
+
+
+def test_ticket_lifetime(torch_cuda, mix):
+    from paper_2305_02064_amd import sar
+    scans, _ = mix
+    sc, plan, pos, echo = scans[0]
+    srv = sar.Server(2 << 30)
+    try:
+        t = srv.submit(plan, pos, echo)
+        srv.wait(t)
+        with pytest.raises(sar.SarError) as ei:
+            sar.sar_poll(srv.handle, t)
+        assert ei.value.status == sar.SAR_ERR_NOT_FOUND
+        with pytest.raises(sar.SarError) as ei:
+            sar.sar_poll(srv.handle, 10 ** 9)
+        assert ei.value.status == sar.SAR_ERR_NOT_FOUND
+    finally:
+        srv.close()
+
+
+def test_destroy_waits_for_pending_scans(torch_cuda, mix):
+    # scans still queued at destroy are run to completion before it returns
+    from paper_2305_02064_amd import sar
+    scans, refs = mix
+    srv = sar.Server(4 << 30)
+    imgs = []
+    for i in range(len(scans)):
+        sc, plan, pos, echo = scans[i]
+        img = plan.new_image()
+        img.fill_(0)
+        torch_cuda.cuda.synchronize()
+        sar.sar_submit(srv.handle, plan.handle, pos, sc.n_pos, echo, 1.0, img)
+        imgs.append(img)
+    srv.close()
+    for i, img in enumerate(imgs):
+        assert rel_l2(img.cpu().numpy(), refs[i].cpu().numpy()) <= SAME_TOL
