@@ -101,6 +101,137 @@ def cpu_baseline(scan, echo_host_fn):
     }
 
 
+def serving_bench(big_scan, big_pos, big_plan, n_requests, rates, seed=0):
+    """Served vs plain per-scan path on a stream of scans shaped like the
+    serving workload: 95% scans of the uneven batch (64 distinct scans, side
+    64-256 positions, 64-256 frequencies), 5% scans of the large freehand size.
+    Echoes are seeded random device tensors (the kernels' work does not depend
+    on the values; accuracy is covered by the parity tests).
+
+    plain:  one sar_reconstruct per scan in arrival order on one stream;
+    served: sar_submit of every scan to one server (continuous admission under
+            an HBM budget, scans overlapping on four streams).
+    Saturation: all requests present at t=0.  Poisson: arrivals at each rate,
+    latency = arrival to completion of the scan's last kernel."""
+    import numpy as np
+    import torch
+    from paper_2305_02064_amd import sar
+    from sarsynth import config4_scan
+
+    dev = torch.device("cuda", 0)
+    distinct = []
+    for sd in range(64):
+        sc = config4_scan(sd, with_echo=False)
+        g = torch.Generator(device=dev)
+        g.manual_seed(10_000 + sd)
+        shape = (sc.n_pos, sc.n_pair, sc.n_freq)
+        echo = torch.complex(torch.randn(shape, generator=g, device=dev), torch.randn(shape, generator=g, device=dev))
+        pos = torch.from_numpy(np.ascontiguousarray(sc.pos)).to(dev)
+        plan = sar.Plan(sc.tx_xy, sc.rx_xy, sc.freq, sc.grid, sc.n_pos, workspace=False)
+        distinct.append((plan, pos, echo, sc.grid.n_voxels))
+    distinct.append((big_plan, big_pos, big_scan.echo, big_scan.grid.n_voxels))
+    rng = np.random.default_rng(seed)
+    seq = [64 if rng.random() < 0.05 else int(rng.integers(64)) for _ in range(n_requests)]
+    ws_max = max(sar.sar_plan_workspace_bytes(distinct[i][0].handle, distinct[i][1].shape[0]) for i in set(seq))
+    ws = torch.empty(ws_max + 256, dtype=torch.uint8, device=dev)
+    ws = ws[(-ws.data_ptr()) % 256:][:ws_max]
+    images = {i: distinct[i][0].new_image() for i in set(seq)}
+    stream = torch.cuda.current_stream()
+    voxels = sum(distinct[i][3] for i in seq)
+
+    def plain_one(i):
+        plan, pos, echo, _ = distinct[i]
+        sar.sar_reconstruct(plan.handle, pos, pos.shape[0], echo, 1.0, images[i], ws, stream)
+
+    # warm both paths on every distinct scan of the sequence
+    for i in set(seq):
+        plain_one(i)
+    torch.cuda.synchronize()
+    budget = max(24 << 30, 4 * ws_max)
+    srv = sar.Server(budget)
+    for t in [srv.submit(distinct[i][0], distinct[i][1], distinct[i][2], images[i]) for i in set(seq)]:
+        srv.wait(t)
+
+    # saturation throughput
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in seq:
+        plain_one(i)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tickets = [srv.submit(distinct[i][0], distinct[i][1], distinct[i][2], images[i]) for i in seq]
+    lat_sat = [srv.wait(t)[0] for t in tickets]
+    t_served = time.perf_counter() - t0
+
+    def pct(v):
+        return {"p50_ms": float(np.percentile(v, 50) * 1e3), "p99_ms": float(np.percentile(v, 99) * 1e3)}
+
+    out = {
+        "workload": (f"{n_requests} requests: 95% uneven-batch scans (64 distinct, 64-256 side, 64-256 freq), "
+                     f"5% 512x256-shot freehand scans; {len(set(seq))} distinct scans, random device echoes"),
+        "voxels_per_request_mean": voxels / n_requests,
+        "saturation": {
+            "plain": {"scans_per_s": n_requests / t_plain, "voxels_per_s": voxels / t_plain},
+            "served": {"scans_per_s": n_requests / t_served, "voxels_per_s": voxels / t_served, **pct(lat_sat)},
+            "speedup": t_plain / t_served,
+        },
+        "poisson": [],
+        "hbm_budget_bytes": budget,
+    }
+    for rate in rates:
+        arr = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+        # plain: each arrival launches its scan on the one stream; completion
+        # seen by polling an event recorded behind it
+        pending = []
+        lat_p = []
+
+        def retire(t0):
+            keep = []
+            for a, e in pending:
+                if e.query():
+                    lat_p.append(time.perf_counter() - t0 - a)
+                else:
+                    keep.append((a, e))
+            pending[:] = keep
+
+        t0 = time.perf_counter()
+        for k, i in enumerate(seq):
+            while time.perf_counter() - t0 < arr[k]:
+                retire(t0)
+            plain_one(i)
+            e = torch.cuda.Event()
+            e.record(stream)
+            pending.append((arr[k], e))
+        while pending:
+            retire(t0)
+        t_p = time.perf_counter() - t0
+        # served
+        lat_s = []
+        live = []
+        t0 = time.perf_counter()
+        for k, i in enumerate(seq):
+            while time.perf_counter() - t0 < arr[k]:
+                still = []
+                for t in live:
+                    done, lat, _ = srv.poll(t)
+                    if done:
+                        lat_s.append(lat)
+                    else:
+                        still.append(t)
+                live = still
+            live.append(srv.submit(distinct[i][0], distinct[i][1], distinct[i][2], images[i]))
+        for t in live:
+            lat_s.append(srv.wait(t)[0])
+        t_s = time.perf_counter() - t0
+        out["poisson"].append({"rate_per_s": rate, "plain": {"scans_per_s": n_requests / t_p, **pct(lat_p)},
+                               "served": {"scans_per_s": n_requests / t_s, **pct(lat_s)}})
+    srv.close()
+    for plan, _, _, _ in distinct[:64]:
+        plan.close()
+    return out
+
+
 def copy_calibration(nbytes, launches=3):
     import torch
     x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -121,6 +252,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-rates", type=str, default="50,200,500")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the library forms each image on a single device (got --gpus {args.gpus})",
@@ -209,6 +343,9 @@ def main():
         },
         "input_generation_s": t_gen,
     }
+    if not args.no_serving:
+        out["serving"] = serving_bench(scan, pos, plan, args.serve_requests,
+                                       [float(r) for r in args.serve_rates.split(",") if r])
     if not args.no_cpu_baseline:
         def echo_host(kk):
             return echo[:, :, :kk].cpu().numpy().astype(np.complex128)
