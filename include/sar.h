@@ -58,6 +58,7 @@ extern "C" {
 
 typedef struct sar_plan_s* sar_plan;
 typedef struct sar_server_s* sar_server;
+typedef struct sar_batch_s* sar_batch;
 typedef void* sar_stream_t; /* a hipStream_t */
 
 typedef enum {
@@ -171,6 +172,36 @@ sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* 
  * the records.  ms must hold sar_plan_info.n_stages doubles. */
 sar_status sar_plan_set_timing(sar_plan plan, int enable);
 sar_status sar_plan_stage_times(sar_plan plan, double* ms, int32_t n, int64_t* n_calls);
+
+/* ---- Fused batches of uneven scans ----
+ * A batch runs the per-scan pipeline (Sec. III) of several scans, each with
+ * its own plan (sizes may differ), in one fused launch per pipeline step:
+ * every kernel grid holds the blocks of all scans that use the same kernel
+ * at that step, each scan reading its arguments from a device table.  The
+ * launch sequence depends only on the plans (per-sample grids are sized for
+ * each plan's max_pos), so it is captured once into a HIP graph and replayed
+ * by every later call.
+ *
+ * sar_batch_create: plans[0..n-1], all on one device, one per item (a plan
+ *   may appear several times); the plans must outlive the batch.  flags:
+ *   SAR_BATCH_NO_GRAPH issues the fused launches directly instead of
+ *   replaying a graph.  Errors: SAR_ERR_INVALID, SAR_ERR_NOMEM.
+ * sar_batch_workspace_bytes: device workspace for one call (sum over items of
+ *   the plan's workspace at its max_pos, each 256-byte aligned).
+ * sar_batch_reconstruct: host arrays of n entries: d_pos[i], n_pos[i]
+ *   (<= the plan's max_pos), d_echo[i], echo_scale[i] (NULL = all 1),
+ *   d_image[i] (device buffers, layouts as sar_reconstruct).  Asynchronous on
+ *   `stream`; calls on one batch are ordered even across streams (the device
+ *   argument tables are shared).  The first call captures the graph.
+ *   Errors: SAR_ERR_INVALID (arguments, per item), SAR_ERR_DEVICE.
+ * sar_batch_destroy: waits for the batch's last call, then releases it. */
+#define SAR_BATCH_NO_GRAPH 0x1u
+sar_status sar_batch_create(const sar_plan* plans, int32_t n, uint32_t flags, sar_batch* out);
+sar_status sar_batch_workspace_bytes(sar_batch batch, size_t* bytes);
+sar_status sar_batch_reconstruct(sar_batch batch, const double* const* d_pos, const int64_t* n_pos,
+                                 const void* const* d_echo, const float* echo_scale, void* const* d_image,
+                                 void* d_workspace, sar_stream_t stream);
+sar_status sar_batch_destroy(sar_batch batch);
 
 /* ---- Serving: continuous admission of scans under a device-memory budget ----
  * The paper forms one image per scan (Sec. III); a server runs that same

@@ -5,6 +5,7 @@
 #include <new>
 #include <string>
 
+#include "launch.hpp"
 #include "sar_internal.hpp"
 
 namespace sar {
@@ -50,6 +51,7 @@ struct Timer {
   hipStream_t s;
   hipEvent_t ev[kNumStages + 1] = {};
   bool on;
+  // enable only with a stream (direct launches); a fused batch is not timed per stage
   Timer(Plan& plan, hipStream_t stream, bool enable) : p(plan), s(stream), on(enable) {
     if (!on) return;
     for (auto& e : ev)
@@ -68,14 +70,14 @@ struct Timer {
   }
 };
 
-sar_status run_front(Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
-                     float2* spec_out, const Workspace& ws, hipStream_t stream, Timer& tm) {
+sar_status run_front(const Plan& p, const double* d_pos, int64_t n_pos, int64_t n_pos_grid, const void* d_echo,
+                     float echo_scale, float2* spec_out, const Workspace& ws, LaunchSink& sink, Timer* tm) {
   sar_status st;
-  tm.mark(0);
-  if ((st = launch_geometry_sort(p, d_pos, n_pos, ws, stream)) != SAR_OK) return st;
-  tm.mark(1);
-  if ((st = launch_gridding(p, n_pos, d_echo, echo_scale, ws, ws.region_a, stream)) != SAR_OK) return st;
-  tm.mark(2);
+  if (tm) tm->mark(0);
+  if ((st = launch_geometry_sort(p, d_pos, n_pos, n_pos_grid, ws, sink)) != SAR_OK) return st;
+  if (tm) tm->mark(1);
+  if ((st = launch_gridding(p, d_echo, echo_scale, ws, ws.region_a, sink)) != SAR_OK) return st;
+  if (tm) tm->mark(2);
   FftLines fx{};
   fx.in = ws.region_a;
   fx.out = ws.region_b;
@@ -91,8 +93,8 @@ sar_status run_front(Plan& p, const double* d_pos, int64_t n_pos, const void* d_
   fx.sign = -1;
   fx.scale = p.d_deapx;
   fx.tw = p.d_tw_mx;
-  if ((st = launch_fft_lines(fx, stream)) != SAR_OK) return st;
-  tm.mark(3);
+  if ((st = launch_fft_lines(fx, sink)) != SAR_OK) return st;
+  if (tm) tm->mark(3);
   FftLines fy{};
   fy.in = ws.region_b;
   fy.out = spec_out;
@@ -108,17 +110,17 @@ sar_status run_front(Plan& p, const double* d_pos, int64_t n_pos, const void* d_
   fy.sign = -1;
   fy.scale = p.d_deapy;
   fy.tw = p.d_tw_my;
-  if ((st = launch_fft_lines(fy, stream)) != SAR_OK) return st;
-  tm.mark(4);
+  if ((st = launch_fft_lines(fy, sink)) != SAR_OK) return st;
+  if (tm) tm->mark(4);
   return SAR_OK;
 }
 
-sar_status run_back(Plan& p, const float2* spec, void* d_image, const Workspace& ws, hipStream_t stream,
-                    Timer& tm, int first_mark) {
+sar_status run_back(const Plan& p, const float2* spec, void* d_image, const Workspace& ws, LaunchSink& sink,
+                    Timer* tm, int first_mark) {
   sar_status st;
-  tm.mark(first_mark);
-  if ((st = launch_stolt(p, spec, ws.region_b, stream)) != SAR_OK) return st;
-  tm.mark(first_mark + 1);
+  if (tm) tm->mark(first_mark);
+  if ((st = launch_stolt(p, spec, ws.region_b, sink)) != SAR_OK) return st;
+  if (tm) tm->mark(first_mark + 1);
   FftLines gy{};
   gy.in = ws.region_b;  // [ny][nx][nz]
   gy.out = ws.region_a; // [ny(v)][nx][nz]
@@ -134,8 +136,8 @@ sar_status run_back(Plan& p, const float2* spec, void* d_image, const Workspace&
   gy.sign = +1;
   gy.scale = p.d_signy;
   gy.tw = p.d_tw_ny;
-  if ((st = launch_fft_lines(gy, stream)) != SAR_OK) return st;
-  tm.mark(first_mark + 2);
+  if ((st = launch_fft_lines(gy, sink)) != SAR_OK) return st;
+  if (tm) tm->mark(first_mark + 2);
   FftLines gx{};
   gx.in = ws.region_a;  // [v][P][w]
   gx.out = (float2*)d_image;  // [u][v][w]
@@ -151,8 +153,8 @@ sar_status run_back(Plan& p, const float2* spec, void* d_image, const Workspace&
   gx.sign = +1;
   gx.scale = p.d_signx;
   gx.tw = p.d_tw_nx;
-  if ((st = launch_fft_lines(gx, stream)) != SAR_OK) return st;
-  tm.mark(first_mark + 3);
+  if ((st = launch_fft_lines(gx, sink)) != SAR_OK) return st;
+  if (tm) tm->mark(first_mark + 3);
   return SAR_OK;
 }
 
@@ -169,12 +171,18 @@ sar_status check_call(sar_plan plan, int64_t n_pos, const void* d_pos, const voi
 
 sar_status reconstruct_on(Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
                           void* d_image, void* d_workspace, hipStream_t stream) {
+  DirectSink sink(stream);
+  return describe_reconstruct(p, d_pos, n_pos, n_pos, d_echo, echo_scale, d_image, d_workspace, sink);
+}
+
+sar_status describe_reconstruct(const Plan& p, const double* d_pos, int64_t n_pos, int64_t n_pos_grid,
+                                const void* d_echo, float echo_scale, void* d_image, void* d_workspace,
+                                LaunchSink& sink) {
   Workspace ws;
-  workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
-  Timer tm(p, stream, false);
-  sar_status st = run_front(p, d_pos, n_pos, d_echo, echo_scale, ws.region_a, ws, stream, tm);
+  workspace_bytes(p, n_pos_grid, &ws, (char*)d_workspace);
+  sar_status st = run_front(p, d_pos, n_pos, n_pos_grid, d_echo, echo_scale, ws.region_a, ws, sink, nullptr);
   if (st != SAR_OK) return st;
-  return run_back(p, ws.region_a, d_image, ws, stream, tm, 4);
+  return run_back(p, ws.region_a, d_image, ws, sink, nullptr, 4);
 }
 
 sar_status check_reconstruct_args(sar_plan plan, int64_t n_pos, const void* pos, const void* echo,
@@ -263,9 +271,10 @@ sar_status sar_reconstruct(sar_plan plan, const double* d_pos, int64_t n_pos, co
   Workspace ws;
   workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
   hipStream_t s = (hipStream_t)stream;
+  DirectSink sink(s);
   Timer tm(p, s, p.timing);
-  if ((st = run_front(p, d_pos, n_pos, d_echo, echo_scale, ws.region_a, ws, s, tm)) != SAR_OK) return st;
-  if ((st = run_back(p, ws.region_a, d_image, ws, s, tm, 4)) != SAR_OK) return st;
+  if ((st = run_front(p, d_pos, n_pos, n_pos, d_echo, echo_scale, ws.region_a, ws, sink, &tm)) != SAR_OK) return st;
+  if ((st = run_back(p, ws.region_a, d_image, ws, sink, &tm, 4)) != SAR_OK) return st;
   tm.commit();
   return SAR_OK;
 }
@@ -278,8 +287,8 @@ sar_status sar_spectrum(sar_plan plan, const double* d_pos, int64_t n_pos, const
   DeviceGuard g(p.device);
   Workspace ws;
   workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
-  Timer tm(p, (hipStream_t)stream, false);
-  return run_front(p, d_pos, n_pos, d_echo, echo_scale, (float2*)d_spectrum, ws, (hipStream_t)stream, tm);
+  DirectSink sink((hipStream_t)stream);
+  return run_front(p, d_pos, n_pos, n_pos, d_echo, echo_scale, (float2*)d_spectrum, ws, sink, nullptr);
 }
 
 sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* d_image, void* d_workspace,
@@ -291,8 +300,8 @@ sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* 
   DeviceGuard g(p.device);
   Workspace ws;
   workspace_bytes(p, 0, &ws, (char*)d_workspace);
-  Timer tm(p, (hipStream_t)stream, false);
-  return run_back(p, (const float2*)d_spectrum, d_image, ws, (hipStream_t)stream, tm, 4);
+  DirectSink sink((hipStream_t)stream);
+  return run_back(p, (const float2*)d_spectrum, d_image, ws, sink, nullptr, 4);
 }
 
 sar_status sar_plan_set_timing(sar_plan plan, int enable) {

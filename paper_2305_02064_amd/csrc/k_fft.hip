@@ -13,20 +13,28 @@
 // centred modes and a per-output scale (deapodisation or +-1 signs).
 
 #include "device_common.hpp"
+#include "launch.hpp"
 #include "sar_internal.hpp"
 
 namespace sar {
 namespace {
 
 template <int L1, int L2, int BC, int SIGN>
-__global__ __launch_bounds__((L1 > L2 ? L1 : L2) * BC) void k_fft_lines(FftLines a) {
+struct FftBody {
+  using Args = FftLines;
+  static constexpr int kThreads = (L1 > L2 ? L1 : L2) * BC;
+  static __device__ __forceinline__ void run(const FftLines& a, uint32_t blk, uint32_t nblk);
+};
+
+template <int L1, int L2, int BC, int SIGN>
+__device__ __forceinline__ void FftBody<L1, L2, BC, SIGN>::run(const FftLines& a, uint32_t blk, uint32_t nblk) {
   constexpr int L = L1 * L2;
   constexpr int RS = (L2 + 1) * BC;  // padded LDS row (one l1) to spread banks
   extern __shared__ float2 lds[];     // [L1][L2 + 1][BC]
   const int64_t nbc = (a.B + BC - 1) / BC;
   // consecutive column groups share cache lines when BC * 8 < 128 bytes: the
   // remap runs them back to back on one XCD so the second finds them in L2
-  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t bid = xcd_remap(blk, nblk);
   const int64_t o = bid / nbc;
   const int64_t bc = bid - o * nbc;
   const int b = threadIdx.x % BC;
@@ -77,42 +85,31 @@ __global__ __launch_bounds__((L1 > L2 ? L1 : L2) * BC) void k_fft_lines(FftLines
 }
 
 template <int L1, int L2, int BC>
-sar_status launch_lb(const FftLines& a, hipStream_t stream) {
-  constexpr int NT = (L1 > L2 ? L1 : L2) * BC;
+sar_status launch_lb(const FftLines& a, LaunchSink& sink) {
   const size_t lds = (size_t)L1 * (L2 + 1) * BC * sizeof(float2);
   const int64_t nbc = (a.B + BC - 1) / BC;
   const int64_t nblk = nbc * a.n_outer;
   if (nblk <= 0) return SAR_OK;
   if (nblk > 0x7fffffffLL) return fail(SAR_ERR_UNSUPPORTED, "FFT batch too large");
-  // blocks may use more than the default 64 KiB of dynamic LDS; the attribute
-  // is set on every launch so it holds on whichever device is current
-  const void* fn = a.sign < 0 ? (const void*)k_fft_lines<L1, L2, BC, -1> : (const void*)k_fft_lines<L1, L2, BC, +1>;
-  if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return check_hip(e, "fft LDS attribute");
-  }
-  if (a.sign < 0)
-    k_fft_lines<L1, L2, BC, -1><<<(unsigned)nblk, NT, lds, stream>>>(a);
-  else
-    k_fft_lines<L1, L2, BC, +1><<<(unsigned)nblk, NT, lds, stream>>>(a);
-  return check_hip(hipGetLastError(), "fft launch");
+  if (a.sign < 0) return launch_body<FftBody<L1, L2, BC, -1>>(sink, (uint32_t)nblk, lds, a, "fft launch");
+  return launch_body<FftBody<L1, L2, BC, +1>>(sink, (uint32_t)nblk, lds, a, "fft launch");
 }
 
 }  // namespace
 
-sar_status launch_fft_lines(const FftLines& a, hipStream_t stream) {
+sar_status launch_fft_lines(const FftLines& a, LaunchSink& sink) {
   // batch columns per block chosen so one block's LDS stays near 64 KiB
   switch (a.L) {
-    case 8: return launch_lb<2, 4, 16>(a, stream);
-    case 16: return launch_lb<4, 4, 16>(a, stream);
-    case 32: return launch_lb<4, 8, 16>(a, stream);
-    case 64: return launch_lb<8, 8, 16>(a, stream);
-    case 128: return launch_lb<8, 16, 16>(a, stream);
-    case 256: return launch_lb<16, 16, 16>(a, stream);
-    case 512: return launch_lb<16, 32, 16>(a, stream);
-    case 1024: return launch_lb<32, 32, 8>(a, stream);
-    case 2048: return launch_lb<32, 64, 4>(a, stream);
-    case 4096: return launch_lb<64, 64, 2>(a, stream);
+    case 8: return launch_lb<2, 4, 16>(a, sink);
+    case 16: return launch_lb<4, 4, 16>(a, sink);
+    case 32: return launch_lb<4, 8, 16>(a, sink);
+    case 64: return launch_lb<8, 8, 16>(a, sink);
+    case 128: return launch_lb<8, 16, 16>(a, sink);
+    case 256: return launch_lb<16, 16, 16>(a, sink);
+    case 512: return launch_lb<16, 32, 16>(a, sink);
+    case 1024: return launch_lb<32, 32, 8>(a, sink);
+    case 2048: return launch_lb<32, 64, 4>(a, sink);
+    case 4096: return launch_lb<64, 64, 2>(a, sink);
     default: return fail(SAR_ERR_UNSUPPORTED, "FFT length not supported: " + std::to_string(a.L));
   }
 }

@@ -9,6 +9,7 @@
 // Within a cell the order is by source index, so results are reproducible.
 
 #include "device_common.hpp"
+#include "launch.hpp"
 #include "sar_internal.hpp"
 
 namespace sar {
@@ -68,28 +69,44 @@ __device__ __forceinline__ void grid_coord(double rel, double scale, int m, int 
 
 __device__ __forceinline__ int wrap(int c, int m) { return c < 0 ? c + m : (c >= m ? c - m : c); }
 
-__global__ void k_zero_i32(int32_t* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
+struct ZeroBody {
+  struct Args {
+    int32_t* p;
+    int64_t n;
+  };
+  static constexpr int kThreads = 256;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
+    const int64_t i = (int64_t)b * kThreads + threadIdx.x;
+    if (i < a.n) a.p[i] = 0;
+  }
+};
 
+// per virtual sample: first-tap cell (the sort key) and its rank in the cell
 template <int W>
-__global__ void k_keys(GeoArgs a, int32_t* __restrict__ key, int32_t* __restrict__ rank,
-                       int32_t* __restrict__ count) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= a.n_v) return;
-  const int64_t m = n / a.n_pair;
-  const int l = (int)(n - m * a.n_pair);
-  const double xv = a.pos[3 * m + 0] + a.pair[4 * l + 0];
-  const double yv = a.pos[3 * m + 1] + a.pair[4 * l + 1];
-  double gx, gy;
-  int cx, cy;
-  grid_coord(xv - a.xc, a.gsx, a.mx, W, gx, cx);
-  grid_coord(yv - a.yc, a.gsy, a.my, W, gy, cy);
-  const int k = wrap(cy, a.my) * a.mx + wrap(cx, a.mx);
-  key[n] = k;
-  rank[n] = atomicAdd(&count[k], 1);
-}
+struct KeysBody {
+  struct Args {
+    GeoArgs g;
+    int32_t* key;
+    int32_t* rank;
+    int32_t* count;
+  };
+  static constexpr int kThreads = 256;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
+    const int64_t n = (int64_t)b * kThreads + threadIdx.x;
+    if (n >= a.g.n_v) return;
+    const int64_t m = n / a.g.n_pair;
+    const int l = (int)(n - m * a.g.n_pair);
+    const double xv = a.g.pos[3 * m + 0] + a.g.pair[4 * l + 0];
+    const double yv = a.g.pos[3 * m + 1] + a.g.pair[4 * l + 1];
+    double gx, gy;
+    int cx, cy;
+    grid_coord(xv - a.g.xc, a.g.gsx, a.g.mx, W, gx, cx);
+    grid_coord(yv - a.g.yc, a.g.gsy, a.g.my, W, gy, cy);
+    const int k = wrap(cy, a.g.my) * a.g.mx + wrap(cx, a.g.mx);
+    a.key[n] = k;
+    a.rank[n] = atomicAdd(&a.count[k], 1);
+  }
+};
 
 // ---- exclusive scan of the per-cell counts (three passes) -----------------
 constexpr int kScanThreads = 1024;
@@ -124,138 +141,190 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* smem_waves, int&
   return incl - v + smem_waves[wave];
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_local(int32_t* __restrict__ data, int64_t n,
-                                                            int32_t* __restrict__ bsum) {
-  __shared__ int smem[65];
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-  int v[kScanItems];
-  int s = 0;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < n) ? data[base + i] : 0;
-    s += v[i];
-  }
-  int total;
-  int run = block_exclusive_scan(s, smem, total);
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < n) data[base + i] = run;
-    run += v[i];
-  }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int32_t* __restrict__ bsum, int nb,
-                                                           int32_t* __restrict__ total_out) {
-  __shared__ int smem[65];
-  __shared__ int carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int c0 = 0; c0 < nb; c0 += kScanChunk) {
-    const int base = c0 + threadIdx.x * kScanItems;
+// pass 1: scan within chunks of kScanChunk counts, chunk totals to bsum
+struct ScanLocalBody {
+  struct Args {
+    int32_t* data;
+    int64_t n;
+    int32_t* bsum;
+  };
+  static constexpr int kThreads = kScanThreads;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
+    __shared__ int smem[65];
+    const int64_t base = (int64_t)b * kScanChunk + (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
     int s = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-      v[i] = (base + i < nb) ? bsum[base + i] : 0;
+      v[i] = (base + i < a.n) ? a.data[base + i] : 0;
       s += v[i];
     }
     int total;
-    int run = block_exclusive_scan(s, smem, total) + carry;
+    int run_ = block_exclusive_scan(s, smem, total);
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i) {
-      if (base + i < nb) bsum[base + i] = run;
-      run += v[i];
+      if (base + i < a.n) a.data[base + i] = run_;
+      run_ += v[i];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) carry += total;
-    __syncthreads();
+    if (threadIdx.x == 0) a.bsum[b] = total;
   }
-  if (threadIdx.x == 0) *total_out = carry;
-}
+};
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* __restrict__ data, int64_t n,
-                                                          const int32_t* __restrict__ bsum) {
-  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
-  const int off = bsum[blockIdx.x];
+// pass 2 (one block): exclusive scan of the chunk totals; grand total out
+struct ScanSumsBody {
+  struct Args {
+    int32_t* bsum;
+    int nb;
+    int32_t* total_out;
+  };
+  static constexpr int kThreads = kScanThreads;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t, uint32_t) {
+    __shared__ int smem[65];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < a.nb; c0 += kScanChunk) {
+      const int base = c0 + threadIdx.x * kScanItems;
+      int v[kScanItems];
+      int s = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i)
-    if (base + i < n) data[base + i] += off;
-}
+      for (int i = 0; i < kScanItems; ++i) {
+        v[i] = (base + i < a.nb) ? a.bsum[base + i] : 0;
+        s += v[i];
+      }
+      int total;
+      int run_ = block_exclusive_scan(s, smem, total) + carry;
+#pragma unroll
+      for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < a.nb) a.bsum[base + i] = run_;
+        run_ += v[i];
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) carry += total;
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *a.total_out = carry;
+  }
+};
 
-__global__ void k_scatter(int64_t n_v, const int32_t* __restrict__ key, const int32_t* __restrict__ rank,
-                          const int32_t* __restrict__ start, int32_t* __restrict__ order) {
-  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= n_v) return;
-  order[start[key[n]] + rank[n]] = (int32_t)n;
-}
+// pass 3: add each chunk's offset
+struct ScanAddBody {
+  struct Args {
+    int32_t* data;
+    int64_t n;
+    const int32_t* bsum;
+  };
+  static constexpr int kThreads = kScanThreads;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
+    const int64_t base = (int64_t)b * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    const int off = a.bsum[b];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+      if (base + i < a.n) a.data[base + i] += off;
+  }
+};
+
+struct ScatterBody {
+  struct Args {
+    int64_t n_v;
+    const int32_t* key;
+    const int32_t* rank;
+    const int32_t* start;
+    int32_t* order;
+  };
+  static constexpr int kThreads = 256;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
+    const int64_t n = (int64_t)b * kThreads + threadIdx.x;
+    if (n >= a.n_v) return;
+    a.order[a.start[a.key[n]] + a.rank[n]] = (int32_t)n;
+  }
+};
 
 // One thread per cell: order the cell's samples by source index.
-__global__ void k_sort_cells(int64_t ncell, const int32_t* __restrict__ start, int32_t* __restrict__ order) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const int s0 = start[c], s1 = start[c + 1];
-  for (int i = s0 + 1; i < s1; ++i) {
-    const int v = order[i];
-    int j = i - 1;
-    while (j >= s0 && order[j] > v) {
-      order[j + 1] = order[j];
-      --j;
+struct SortCellsBody {
+  struct Args {
+    int64_t ncell;
+    const int32_t* start;
+    int32_t* order;
+  };
+  static constexpr int kThreads = 256;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
+    const int64_t c = (int64_t)b * kThreads + threadIdx.x;
+    if (c >= a.ncell) return;
+    const int s0 = a.start[c], s1 = a.start[c + 1];
+    for (int i = s0 + 1; i < s1; ++i) {
+      const int v = a.order[i];
+      int j = i - 1;
+      while (j >= s0 && a.order[j] > v) {
+        a.order[j + 1] = a.order[j];
+        --j;
+      }
+      a.order[j + 1] = v;
     }
-    order[j + 1] = v;
   }
-}
+};
 
 // One thread per sorted slot: the record of the slot's sample, its geometry
 // recomputed in float64 from the shot position.
 template <int W>
-__global__ void k_records(GeoArgs a, const int32_t* __restrict__ order, SampleRec<W>* __restrict__ rec) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.n_v) return;
-  const int64_t n = order[s];
-  const int64_t m = n / a.n_pair;
-  const int l = (int)(n - m * a.n_pair);
-  const double xv = a.pos[3 * m + 0] + a.pair[4 * l + 0];
-  const double yv = a.pos[3 * m + 1] + a.pair[4 * l + 1];
-  const double dzv = a.pos[3 * m + 2] - a.z_ref;
-  double gx, gy;
-  int cx, cy;
-  grid_coord(xv - a.xc, a.gsx, a.mx, W, gx, cx);
-  grid_coord(yv - a.yc, a.gsy, a.my, W, gy, cy);
-  SampleRec<W> r;
-  r.src = (int32_t)n;
-  r.cx = (int16_t)wrap(wrap(cx, a.mx) + W - 1, a.mx);
-  r.cy = (int16_t)wrap(wrap(cy, a.my) + W - 1, a.my);
-  r.beta = a.beta_sign * dzv + a.pair[4 * l + 2];
-  const double fx = (double)cx - gx;
-  const double fy = (double)cy - gy;
+struct RecordsBody {
+  struct Args {
+    GeoArgs g;
+    const int32_t* order;
+    SampleRec<W>* rec;
+  };
+  static constexpr int kThreads = 256;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
+    const int64_t s = (int64_t)b * kThreads + threadIdx.x;
+    if (s >= a.g.n_v) return;
+    const int64_t n = a.order[s];
+    const int64_t m = n / a.g.n_pair;
+    const int l = (int)(n - m * a.g.n_pair);
+    const double xv = a.g.pos[3 * m + 0] + a.g.pair[4 * l + 0];
+    const double yv = a.g.pos[3 * m + 1] + a.g.pair[4 * l + 1];
+    const double dzv = a.g.pos[3 * m + 2] - a.g.z_ref;
+    double gx, gy;
+    int cx, cy;
+    grid_coord(xv - a.g.xc, a.g.gsx, a.g.mx, W, gx, cx);
+    grid_coord(yv - a.g.yc, a.g.gsy, a.g.my, W, gy, cy);
+    SampleRec<W> r;
+    r.src = (int32_t)n;
+    r.cx = (int16_t)wrap(wrap(cx, a.g.mx) + W - 1, a.g.mx);
+    r.cy = (int16_t)wrap(wrap(cy, a.g.my) + W - 1, a.g.my);
+    r.beta = a.g.beta_sign * dzv + a.g.pair[4 * l + 2];
+    const double fx = (double)cx - gx;
+    const double fy = (double)cy - gy;
 #pragma unroll
-  for (int j = 0; j < W; ++j) {
-    r.wx[j] = kb_weight(fx + j, W, a.kb_beta, a.inv_i0_beta);
-    r.wy[j] = kb_weight(fy + j, W, a.kb_beta, a.inv_i0_beta);
+    for (int j = 0; j < W; ++j) {
+      r.wx[j] = kb_weight(fx + j, W, a.g.kb_beta, a.g.inv_i0_beta);
+      r.wy[j] = kb_weight(fy + j, W, a.g.kb_beta, a.g.inv_i0_beta);
+    }
+    a.rec[s] = r;
   }
-  rec[s] = r;
-}
+};
+
+uint32_t blocks_for(int64_t n, int threads) { return (uint32_t)((n + threads - 1) / threads); }
 
 template <int W>
-sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, const Workspace& ws,
-                           hipStream_t stream) {
+sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, int64_t n_pos_grid,
+                           const Workspace& ws, LaunchSink& sink) {
   const int64_t n_v = n_pos * p.n_pair;
+  const int64_t n_v_grid = n_pos_grid * p.n_pair;
   const int64_t ncell = (int64_t)p.mx * p.my;
-  GeoArgs a;
-  a.pos = d_pos;
-  a.pair = p.d_pair;
-  a.n_v = n_v;
-  a.n_pair = p.n_pair;
-  a.xc = p.xc;
-  a.yc = p.yc;
-  a.gsx = (double)p.mx / ((double)p.nx * p.dx);
-  a.gsy = (double)p.my / ((double)p.ny * p.dy);
-  a.mx = p.mx;
-  a.my = p.my;
-  a.z_ref = p.z_ref;
-  a.beta_sign = p.beta_sign;
-  a.kb_beta = p.kb_beta;
+  GeoArgs g;
+  g.pos = d_pos;
+  g.pair = p.d_pair;
+  g.n_v = n_v;
+  g.n_pair = p.n_pair;
+  g.xc = p.xc;
+  g.yc = p.yc;
+  g.gsx = (double)p.mx / ((double)p.nx * p.dx);
+  g.gsy = (double)p.my / ((double)p.ny * p.dy);
+  g.mx = p.mx;
+  g.my = p.my;
+  g.z_ref = p.z_ref;
+  g.beta_sign = p.beta_sign;
+  g.kb_beta = p.kb_beta;
   // 1 / I0(beta) evaluated with the same series on the host
   {
     const double q = 0.25 * p.kb_beta * p.kb_beta;
@@ -265,37 +334,41 @@ sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, co
       sum += term;
       if (term < 1e-17 * sum) break;
     }
-    a.inv_i0_beta = 1.0 / sum;
+    g.inv_i0_beta = 1.0 / sum;
   }
-  const int tb = 256;
-  k_zero_i32<<<(unsigned)((ncell + 1 + tb - 1) / tb), tb, 0, stream>>>(ws.cell_start, ncell + 1);
-  if (n_v > 0)
-    k_keys<W><<<(unsigned)((n_v + tb - 1) / tb), tb, 0, stream>>>(a, ws.key, ws.rank, ws.cell_start);
+  sar_status st;
+  const char* what = "geometry/sort launch";
+  if ((st = launch_body<ZeroBody>(sink, blocks_for(ncell + 1, 256), 0, {ws.cell_start, ncell + 1}, what)) != SAR_OK)
+    return st;
+  if ((st = launch_body<KeysBody<W>>(sink, blocks_for(n_v_grid, 256), 0, {g, ws.key, ws.rank, ws.cell_start},
+                                     what)) != SAR_OK)
+    return st;
   const int nb = (int)((ncell + kScanChunk - 1) / kScanChunk);
   int32_t* bsum = ws.cell_start + ncell + 1;
-  k_scan_local<<<nb, kScanThreads, 0, stream>>>(ws.cell_start, ncell, bsum);
-  k_scan_sums<<<1, kScanThreads, 0, stream>>>(bsum, nb, ws.cell_start + ncell);
-  k_scan_add<<<nb, kScanThreads, 0, stream>>>(ws.cell_start, ncell, bsum);
-  if (n_v > 0) {
-    k_scatter<<<(unsigned)((n_v + tb - 1) / tb), tb, 0, stream>>>(n_v, ws.key, ws.rank, ws.cell_start,
-                                                                  ws.order);
-    k_sort_cells<<<(unsigned)((ncell + tb - 1) / tb), tb, 0, stream>>>(ncell, ws.cell_start, ws.order);
-    k_records<W><<<(unsigned)((n_v + tb - 1) / tb), tb, 0, stream>>>(a, ws.order, (SampleRec<W>*)ws.rec);
-  }
-  return check_hip(hipGetLastError(), "geometry/sort launch");
+  if ((st = launch_body<ScanLocalBody>(sink, nb, 0, {ws.cell_start, ncell, bsum}, what)) != SAR_OK) return st;
+  if ((st = launch_body<ScanSumsBody>(sink, 1, 0, {bsum, nb, ws.cell_start + ncell}, what)) != SAR_OK) return st;
+  if ((st = launch_body<ScanAddBody>(sink, nb, 0, {ws.cell_start, ncell, bsum}, what)) != SAR_OK) return st;
+  if ((st = launch_body<ScatterBody>(sink, blocks_for(n_v_grid, 256), 0,
+                                     {n_v, ws.key, ws.rank, ws.cell_start, ws.order}, what)) != SAR_OK)
+    return st;
+  if ((st = launch_body<SortCellsBody>(sink, blocks_for(ncell, 256), 0, {ncell, ws.cell_start, ws.order}, what)) !=
+      SAR_OK)
+    return st;
+  return launch_body<RecordsBody<W>>(sink, blocks_for(n_v_grid, 256), 0,
+                                     {g, ws.order, (SampleRec<W>*)ws.rec}, what);
 }
 
 }  // namespace
 
-sar_status launch_geometry_sort(const Plan& p, const double* d_pos, int64_t n_pos, const Workspace& ws,
-                                hipStream_t stream) {
+sar_status launch_geometry_sort(const Plan& p, const double* d_pos, int64_t n_pos, int64_t n_pos_grid,
+                                const Workspace& ws, LaunchSink& sink) {
   switch (p.w) {
-    case 3: return geometry_sort_w<3>(p, d_pos, n_pos, ws, stream);
-    case 4: return geometry_sort_w<4>(p, d_pos, n_pos, ws, stream);
-    case 5: return geometry_sort_w<5>(p, d_pos, n_pos, ws, stream);
-    case 6: return geometry_sort_w<6>(p, d_pos, n_pos, ws, stream);
-    case 7: return geometry_sort_w<7>(p, d_pos, n_pos, ws, stream);
-    case 8: return geometry_sort_w<8>(p, d_pos, n_pos, ws, stream);
+    case 3: return geometry_sort_w<3>(p, d_pos, n_pos, n_pos_grid, ws, sink);
+    case 4: return geometry_sort_w<4>(p, d_pos, n_pos, n_pos_grid, ws, sink);
+    case 5: return geometry_sort_w<5>(p, d_pos, n_pos, n_pos_grid, ws, sink);
+    case 6: return geometry_sort_w<6>(p, d_pos, n_pos, n_pos_grid, ws, sink);
+    case 7: return geometry_sort_w<7>(p, d_pos, n_pos, n_pos_grid, ws, sink);
+    case 8: return geometry_sort_w<8>(p, d_pos, n_pos, n_pos_grid, ws, sink);
     default: return fail(SAR_ERR_UNSUPPORTED, "kernel width not compiled");
   }
 }

@@ -33,6 +33,7 @@
 #include <cstddef>
 
 #include "device_common.hpp"
+#include "launch.hpp"
 #include "sar_internal.hpp"
 
 // Repeats M(I) for I = 0 .. 191 (covers NBY * NBX up to (4 + 7) * (8 + 7) = 165).
@@ -79,7 +80,14 @@ __device__ __forceinline__ void dma_quad(const void* src, void* lds_base) {
 }
 
 template <int W, int ET>
-__global__ __launch_bounds__(64) void k_grid(GridArgs a) {
+struct GridBody {
+  using Args = GridArgs;
+  static constexpr int kThreads = 64;
+  static __device__ __forceinline__ void run(const GridArgs& a, uint32_t blk, uint32_t nblk);
+};
+
+template <int W, int ET>
+__device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t blk, uint32_t nblk) {
   constexpr int NBX = TX + W - 1;     // last-tap column offsets touching a tile
   constexpr int NBY = TY + W - 1;     // last-tap row offsets touching a tile
   constexpr int NSEG = 2 * NBY;       // each row of cells may split at the x wrap
@@ -93,7 +101,7 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
 
   // row-major tile order (x fastest, frequency chunk slowest); measured
   // faster than narrower strip orders for the serpentine scans
-  const uint32_t work = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t work = xcd_remap(blk, nblk);
   const int tx = (int)(work % (uint32_t)a.ntx);
   const uint32_t rest = work / (uint32_t)a.ntx;
   const int ty = (int)(rest % (uint32_t)a.nty);
@@ -350,7 +358,7 @@ __global__ __launch_bounds__(64) void k_grid(GridArgs a) {
 
 template <int W>
 sar_status grid_w(const Plan& p, const void* d_echo, float echo_scale, const Workspace& ws, float2* grid,
-                  hipStream_t stream) {
+                  LaunchSink& sink) {
   GridArgs a;
   a.rec = ws.rec;
   a.cell_start = ws.cell_start;
@@ -366,19 +374,16 @@ sar_status grid_w(const Plan& p, const void* d_echo, float echo_scale, const Wor
   a.nty = p.my / TY;
   const int nfc = (p.nf + 64 * FPL - 1) / (64 * FPL);
   const int64_t nblk = (int64_t)a.ntx * a.nty * nfc;
-  if (p.echo_type == SAR_ECHO_C64)
-    k_grid<W, SAR_ECHO_C64><<<(unsigned)nblk, 64, 0, stream>>>(a);
-  else
-    k_grid<W, SAR_ECHO_F16X2><<<(unsigned)nblk, 64, 0, stream>>>(a);
-  return check_hip(hipGetLastError(), "gridding launch");
+  if (p.echo_type == SAR_ECHO_C64) return launch_body<GridBody<W, SAR_ECHO_C64>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
+  return launch_body<GridBody<W, SAR_ECHO_F16X2>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
 }
 
 }  // namespace grid_impl
 
 #define SAR_INSTANTIATE_GRID(W)                                                                    \
   sar_status launch_gridding_w##W(const Plan& p, const void* d_echo, float echo_scale,              \
-                                  const Workspace& ws, float2* grid, hipStream_t stream) {          \
-    return grid_impl::grid_w<W>(p, d_echo, echo_scale, ws, grid, stream);                          \
+                                  const Workspace& ws, float2* grid, LaunchSink& sink) {            \
+    return grid_impl::grid_w<W>(p, d_echo, echo_scale, ws, grid, sink);                            \
   }
 
 }  // namespace sar

@@ -20,6 +20,7 @@
 // use plain inverse DFTs on centred mode indices is folded in here.
 
 #include "device_common.hpp"
+#include "launch.hpp"
 #include "sar_internal.hpp"
 
 namespace sar {
@@ -52,7 +53,14 @@ __device__ __forceinline__ float es_weight(float d, float beta) {
 }
 
 template <int MZ, int WZ>
-__global__ __launch_bounds__(64 * kWaves) void k_stolt(StoltArgs a) {
+struct StoltBody {
+  using Args = StoltArgs;
+  static constexpr int kThreads = 64 * kWaves;
+  static __device__ __forceinline__ void run(const StoltArgs& a, uint32_t blk, uint32_t nblk);
+};
+
+template <int MZ, int WZ>
+__device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint32_t blk, uint32_t nblk) {
   constexpr int L2 = MZ / kG;       // points per lane in the first FFT pass
   constexpr int WWIN = WZ + 2;      // register window of cells per lane
   static_assert(MZ % kG == 0 && MZ <= 1024, "Stolt grid of 64..1024 cells");
@@ -67,7 +75,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_stolt(StoltArgs a) {
   const int per = (a.nf + kG - 1) / kG;  // contiguous frequencies per lane
   const int64_t ngroups = (a.ncol + kCols - 1) / kCols;
 
-  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+  for (int64_t grp = blk; grp < ngroups; grp += nblk) {
     const int64_t col = grp * kCols + cl;
     const bool live = col < a.ncol;
     const int64_t colc = live ? col : 0;
@@ -164,21 +172,20 @@ __global__ __launch_bounds__(64 * kWaves) void k_stolt(StoltArgs a) {
 }
 
 template <int MZ>
-sar_status stolt_mz(const Plan& p, const StoltArgs& a, hipStream_t stream) {
+sar_status stolt_mz(const Plan& p, const StoltArgs& a, LaunchSink& sink) {
   // enough blocks to fill every CU several times over; each loops over groups
   const int64_t ngroups = (a.ncol + kCols - 1) / kCols;
   const int64_t nblk = ngroups < 256 * 8 ? ngroups : 256 * 8;
   switch (p.wz) {
-    case 6: k_stolt<MZ, 6><<<(unsigned)nblk, 64 * kWaves, 0, stream>>>(a); break;
-    case 8: k_stolt<MZ, 8><<<(unsigned)nblk, 64 * kWaves, 0, stream>>>(a); break;
+    case 6: return launch_body<StoltBody<MZ, 6>>(sink, (uint32_t)nblk, 0, a, "stolt launch");
+    case 8: return launch_body<StoltBody<MZ, 8>>(sink, (uint32_t)nblk, 0, a, "stolt launch");
     default: return fail(SAR_ERR_UNSUPPORTED, "Stolt kernel width not compiled");
   }
-  return check_hip(hipGetLastError(), "stolt launch");
 }
 
 }  // namespace
 
-sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, hipStream_t stream) {
+sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, LaunchSink& sink) {
   StoltArgs a;
   a.spec = spec;
   a.zc = zcube;
@@ -198,11 +205,11 @@ sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, hipStr
   a.ncol = (int64_t)p.nx * p.ny;
   if (a.ncol == 0) return SAR_OK;
   switch (p.mz) {
-    case 64: return stolt_mz<64>(p, a, stream);
-    case 128: return stolt_mz<128>(p, a, stream);
-    case 256: return stolt_mz<256>(p, a, stream);
-    case 512: return stolt_mz<512>(p, a, stream);
-    case 1024: return stolt_mz<1024>(p, a, stream);
+    case 64: return stolt_mz<64>(p, a, sink);
+    case 128: return stolt_mz<128>(p, a, sink);
+    case 256: return stolt_mz<256>(p, a, sink);
+    case 512: return stolt_mz<512>(p, a, sink);
+    case 1024: return stolt_mz<1024>(p, a, sink);
     default: return fail(SAR_ERR_UNSUPPORTED, "Stolt grid size not supported");
   }
 }

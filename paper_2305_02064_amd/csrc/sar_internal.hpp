@@ -83,11 +83,16 @@ void set_error(const std::string& msg);
 sar_status fail(sar_status st, const std::string& msg);
 sar_status check_hip(hipError_t e, const char* what);
 
-// stage launchers (all asynchronous on `stream`)
-sar_status launch_geometry_sort(const Plan& p, const double* d_pos, int64_t n_pos, const Workspace& ws,
-                                hipStream_t stream);
-sar_status launch_gridding(const Plan& p, int64_t n_pos, const void* d_echo, float echo_scale,
-                           const Workspace& ws, float2* grid, hipStream_t stream);
+class LaunchSink;  // launch.hpp
+
+// stage launchers: describe the stage's kernels to `sink` (launched at once on
+// a stream, or collected into a fused batch).  n_pos_grid >= n_pos sizes the
+// per-sample grids (a batch sizes them for max_pos so that one captured graph
+// serves every scan size); kernels stop at n_pos.
+sar_status launch_geometry_sort(const Plan& p, const double* d_pos, int64_t n_pos, int64_t n_pos_grid,
+                                const Workspace& ws, LaunchSink& sink);
+sar_status launch_gridding(const Plan& p, const void* d_echo, float echo_scale, const Workspace& ws, float2* grid,
+                           LaunchSink& sink);
 // batched 1-D FFT along a strided axis with a contiguous batch dimension:
 // in(o, l, b) = in[o*s_in_o + l*s_in_l + b], l < L, b < B;
 // out(o, P, b) = scale[P] * X(o, k(P), b) at out[o*s_out_o + P*s_out_k + b],
@@ -105,12 +110,16 @@ struct FftLines {
   const float* scale;
   const float2* tw;  // exp(sign j 2 pi i / L), i < L
 };
-sar_status launch_fft_lines(const FftLines& a, hipStream_t stream);
-sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, hipStream_t stream);
+sar_status launch_fft_lines(const FftLines& a, LaunchSink& sink);
+sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, LaunchSink& sink);
 
 // whole per-scan pipeline on `stream` without stage timing (used by the server)
 sar_status reconstruct_on(Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
                           void* d_image, void* d_workspace, hipStream_t stream);
+// whole per-scan pipeline described to a sink (used by fused batches)
+sar_status describe_reconstruct(const Plan& p, const double* d_pos, int64_t n_pos, int64_t n_pos_grid,
+                                const void* d_echo, float echo_scale, void* d_image, void* d_workspace,
+                                LaunchSink& sink);
 // argument checks shared by sar_reconstruct and sar_submit (sets the error text)
 sar_status check_reconstruct_args(sar_plan plan, int64_t n_pos, const void* pos, const void* echo,
                                   const void* image);

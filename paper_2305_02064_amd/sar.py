@@ -31,6 +31,7 @@ STATUS_NAMES = {0: "SAR_OK", 1: "SAR_ERR_INVALID", 2: "SAR_ERR_NOMEM", 3: "SAR_E
 SAR_ECHO_C64 = 0
 SAR_ECHO_F16X2 = 1
 SAR_NO_COMPENSATION = 0x1
+SAR_BATCH_NO_GRAPH = 0x1
 
 STAGES = ("geometry+sort", "gridding", "fft_x", "fft_y", "stolt", "ifft_y", "ifft_x")
 
@@ -95,6 +96,11 @@ def library():
         "sar_submit": ([vp, vp, vp, i64, vp, ctypes.c_int, f32, vp, ctypes.POINTER(ctypes.c_uint64)], i32),
         "sar_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)], i32),
         "sar_server_destroy": ([vp], i32),
+        "sar_batch_create": ([ctypes.POINTER(vp), i32, ctypes.c_uint32, ctypes.POINTER(vp)], i32),
+        "sar_batch_workspace_bytes": ([vp, ctypes.POINTER(ctypes.c_size_t)], i32),
+        "sar_batch_reconstruct": ([vp, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(vp),
+                                   ctypes.POINTER(f32), ctypes.POINTER(vp), vp, vp], i32),
+        "sar_batch_destroy": ([vp], i32),
         "sar_last_error": ([], ctypes.c_char_p),
         "sar_version": ([], ctypes.c_char_p),
     }
@@ -249,6 +255,53 @@ def sar_poll(server, ticket):
 
 def sar_server_destroy(server):
     _check(library().sar_server_destroy(server))
+
+
+class Batch:
+    """A fused batch (sar_batch_*): one plan per item; reconstruct() images
+    every item in one fused launch per pipeline step (a captured HIP graph
+    unless graph=False)."""
+
+    def __init__(self, plans, graph=True):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(library().sar_batch_create(arr, len(self.plans), 0 if graph else SAR_BATCH_NO_GRAPH,
+                                          ctypes.byref(h)))
+        self.handle = h
+        b = ctypes.c_size_t()
+        _check(library().sar_batch_workspace_bytes(h, ctypes.byref(b)))
+        nbytes = max(int(b.value), 256)
+        dev = self.plans[0].device
+        self._ws_buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self._ws_buf.data_ptr()) % 256
+        self.ws = self._ws_buf[off:off + nbytes]
+
+    def reconstruct(self, pos, echo, images=None, echo_scale=None, stream=None):
+        n = len(self.plans)
+        if len(pos) != n or len(echo) != n:
+            raise ValueError(f"need {n} position and echo tensors")
+        images = [p.new_image() for p in self.plans] if images is None else images
+        vp = ctypes.c_void_p
+        P = (vp * n)(*[_dptr(t, "pos", torch.float64).value for t in pos])
+        N = (ctypes.c_int64 * n)(*[t.shape[0] for t in pos])
+        E = (vp * n)(*[_dptr(t, "echo").value for t in echo])
+        S = (ctypes.c_float * n)(*([1.0] * n if echo_scale is None else [float(x) for x in echo_scale]))
+        I = (vp * n)(*[_dptr(t, "image", torch.complex64).value for t in images])
+        _check(library().sar_batch_reconstruct(self.handle, P, N, E, S, I, _dptr(self.ws, "workspace"),
+                                               _stream(stream)))
+        return images
+
+    def close(self):
+        if self.handle is not None:
+            library().sar_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -97,3 +97,18 @@ def test_server_null_and_budget_arguments():
     done = ctypes.c_int()
     assert lib.sar_poll(None, 1, ctypes.byref(done), None) == sar.SAR_ERR_INVALID
     assert lib.sar_server_destroy(None) == sar.SAR_OK
+
+
+def test_batch_null_arguments():
+    sar = _sar()
+    lib = sar.library()
+    h = ctypes.c_void_p()
+    assert lib.sar_batch_create(None, 0, 0, ctypes.byref(h)) == sar.SAR_ERR_INVALID
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.sar_batch_create(arr, 1, 0, ctypes.byref(h)) == sar.SAR_ERR_INVALID
+    assert "NULL" in sar.sar_last_error()
+    assert lib.sar_batch_create(arr, 1, 0, None) == sar.SAR_ERR_INVALID
+    b = ctypes.c_size_t()
+    assert lib.sar_batch_workspace_bytes(None, ctypes.byref(b)) == sar.SAR_ERR_INVALID
+    assert lib.sar_batch_reconstruct(None, None, None, None, None, None, None, None) == sar.SAR_ERR_INVALID
+    assert lib.sar_batch_destroy(None) == sar.SAR_OK

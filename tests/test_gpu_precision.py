@@ -1,0 +1,83 @@
+"""Precision study: the FP32 echo path and the FP16 echo storage path (one
+per-scan scale, max(|Re|, |Im|) mapped to 2^15, FP64 phase arguments and grid
+offsets in both) against the FP64 oracle, on the tiny scan (whole image) and
+on the large freehand scan (whole z planes of a sparse-echo image).  Reports
+relative L2 error and the peak-voxel offset (0 = exact) per setting; both
+settings must meet the method's bar of 1e-3 with an exact peak."""
+
+import numpy as np
+import pytest
+
+import oracle
+from sarsynth import config1_scan
+from tests.sar_testutil import make_plan, peak_index, peak_ok, rel_l2, to_device
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _peak_offset(img, ref):
+    a = np.array(peak_index(img))
+    b = np.array(peak_index(ref))
+    return int(np.abs(a - b).max())
+
+
+@pytest.mark.parametrize("setting", ["fp32-echo", "fp16-echo"])
+def test_precision_tiny_scan(torch_cuda, setting):
+    from paper_2305_02064_amd import sar
+    scan = config1_scan(0)
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, scan.grid)
+    half = setting == "fp16-echo"
+    plan = make_plan(scan, echo_type=sar.SAR_ECHO_F16X2 if half else sar.SAR_ECHO_C64)
+    pos, echo, scale = to_device(scan, half=half)
+    img = plan.reconstruct(pos, echo, echo_scale=scale).cpu().numpy()
+    err = rel_l2(img, ref)
+    off = _peak_offset(img, ref)
+    print(f"precision tiny {setting}: rel-L2 {err:.3e}, peak offset {off} voxels")
+    assert err <= TOL
+    assert peak_ok(img, ref)
+
+
+@pytest.fixture(scope="module")
+def big_sparse(torch_cuda):
+    torch = torch_cuda
+    from sarsynth import config2_scan
+    scan = config2_scan(0, device=torch.device("cuda", 0))
+    rng = np.random.default_rng(12)
+    shots = np.sort(rng.choice(scan.n_pos, 24, replace=False))
+    idx = torch.from_numpy(shots).cuda()
+    e_sparse = torch.zeros_like(scan.echo)
+    e_sparse[idx] = scan.echo[idx]
+    w_list = [40, 128, 200]
+    g = scan.grid
+    spec = oracle.spectrum_direct(scan.pos[shots], scan.tx_xy, scan.rx_xy, scan.freq,
+                                  e_sparse[idx].cpu().numpy(), g)
+    ref = oracle.image_planes_from_spectrum(spec, scan.freq, g, w_list)
+    scan.echo = e_sparse
+    return scan, w_list, ref
+
+
+@pytest.mark.parametrize("setting", ["fp32-echo", "fp16-echo"])
+def test_precision_large_scan_planes(big_sparse, setting):
+    from paper_2305_02064_amd import sar
+    scan, w_list, ref = big_sparse
+    half = setting == "fp16-echo"
+    plan = make_plan(scan, echo_type=sar.SAR_ECHO_F16X2 if half else sar.SAR_ECHO_C64)
+    pos, echo, scale = to_device(scan, half=half)
+    img = plan.reconstruct(pos, echo, echo_scale=scale)[:, :, w_list].cpu().numpy()
+    err = rel_l2(img, ref)
+    offs = [_peak_offset(img[:, :, j], ref[:, :, j]) for j in range(len(w_list))]
+    print(f"precision large {setting}: planes {w_list} rel-L2 {err:.3e}, per-plane peak offsets {offs}")
+    plan.close()
+    assert err <= TOL
+    for j in range(len(w_list)):
+        assert peak_ok(img[:, :, j], ref[:, :, j])
