@@ -210,8 +210,9 @@ sar_status sar_batch_destroy(sar_batch batch);
  *
  * sar_server_create: a server on HIP device `device` owning one arena of
  *   hbm_budget_bytes of device memory (rounded down to 256 bytes), four HIP
- *   streams and a worker thread.  Errors: SAR_ERR_INVALID (no such device,
- *   budget < 256 bytes), SAR_ERR_NOMEM (arena allocation failed).
+ *   streams, a worker thread and 8 MiB each of pinned host and device memory
+ *   for argument tables.  Errors: SAR_ERR_INVALID (no such device, budget <
+ *   256 bytes), SAR_ERR_NOMEM (an allocation failed).
  *
  * sar_submit: queue one scan; returns at once with a ticket.
  *   plan           a plan created on the server's device; it must outlive the request
@@ -223,8 +224,10 @@ sar_status sar_batch_destroy(sar_batch batch);
  *   The caller must keep every buffer unchanged until sar_poll reports the
  *   ticket done.  Requests are admitted in arrival order as soon as their
  *   memory (sar_plan_workspace_bytes, plus the uploaded inputs for host
- *   inputs) fits in the arena and fewer than eight scans are in flight;
- *   admitted scans run concurrently on the least-loaded stream.
+ *   inputs) fits in the arena, with at most 32 scans in flight.  The scans
+ *   admitted together (up to 16) form one unit: one scan runs its own
+ *   kernels, several run in fused launches as in a batch; each unit goes to
+ *   the least-loaded stream, so units overlap on the device.
  *   Errors: SAR_ERR_INVALID (arguments, plan on another device),
  *   SAR_ERR_NOMEM (the request alone exceeds the whole budget; a request
  *   that merely does not fit yet waits), SAR_ERR_BUSY (server shutting down).

@@ -169,7 +169,7 @@ sar_status check_call(sar_plan plan, int64_t n_pos, const void* d_pos, const voi
 
 }  // namespace
 
-sar_status reconstruct_on(Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
+sar_status reconstruct_on(const Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
                           void* d_image, void* d_workspace, hipStream_t stream) {
   DirectSink sink(stream);
   return describe_reconstruct(p, d_pos, n_pos, n_pos, d_echo, echo_scale, d_image, d_workspace, sink);

@@ -162,10 +162,19 @@ sar_status describe_all(BatchState& b, const double* const* pos, const int64_t* 
   return SAR_OK;
 }
 
-sar_status enqueue_groups(const BatchState& b, hipStream_t s) {
-  for (const auto& g : b.groups) {
-    const void* args = b.d_blob + g.off_args;
-    const void* items = b.d_blob + g.off_items;
+sar_status set_lds_attributes(const std::vector<Group>& groups) {
+  for (const auto& gr : groups)
+    if (gr.shmem > 65536) {
+      const hipError_t e = hipFuncSetAttribute(gr.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gr.shmem);
+      if (e != hipSuccess) return check_hip(e, "batch LDS attribute");
+    }
+  return SAR_OK;
+}
+
+sar_status enqueue_groups(const std::vector<Group>& groups, const char* d_blob, hipStream_t s) {
+  for (const auto& g : groups) {
+    const void* args = d_blob + g.off_args;
+    const void* items = d_blob + g.off_items;
     int n = (int)g.items.size();
     void* kargs[] = {(void*)&args, (void*)&items, (void*)&n};
     sar_status st =
@@ -244,10 +253,7 @@ sar_status sar_batch_create(const sar_plan* plans, int32_t n, uint32_t flags, sa
   if (st == SAR_OK) {
     b.blob_bytes = build_groups(sinks, b.groups);
     // kernels with more than the default 64 KiB of dynamic LDS (set before any capture)
-    for (const auto& gr : b.groups)
-      if (st == SAR_OK && gr.shmem > 65536)
-        st = check_hip(hipFuncSetAttribute(gr.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gr.shmem),
-                       "batch LDS attribute");
+    st = set_lds_attributes(b.groups);
   }
   if (st == SAR_OK) {
     if (hipMalloc((void**)&b.d_blob, std::max<size_t>(b.blob_bytes, kAlign)) != hipSuccess) {
@@ -308,7 +314,7 @@ sar_status sar_batch_reconstruct(sar_batch batch, const double* const* d_pos, co
   if ((st = check_hip(hipEventRecord(b.uploaded, s), "event record")) != SAR_OK) return st;
   b.upload_pending = true;
   if (b.flags & SAR_BATCH_NO_GRAPH) {
-    if ((st = enqueue_groups(b, s)) != SAR_OK) return st;
+    if ((st = enqueue_groups(b.groups, b.d_blob, s)) != SAR_OK) return st;
   } else {
     if ((st = launch_graph(b, s)) != SAR_OK) return st;
   }
@@ -337,7 +343,7 @@ sar_status launch_graph(BatchState& b, hipStream_t s) {
     if ((st = check_hip(hipStreamBeginCapture(b.cap_stream, hipStreamCaptureModeThreadLocal), "begin capture")) !=
         SAR_OK)
       return st;
-    st = enqueue_groups(b, b.cap_stream);
+    st = enqueue_groups(b.groups, b.d_blob, b.cap_stream);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(b.cap_stream, &graph);
     if (st != SAR_OK) {
@@ -355,4 +361,38 @@ sar_status launch_graph(BatchState& b, hipStream_t s) {
 }
 
 }  // namespace
+}  // namespace sar
+
+namespace sar {
+
+sar_status launch_fused(const std::vector<FusedItem>& items, char* d_table, char* h_table, size_t capacity,
+                        hipStream_t stream) {
+  std::vector<RecordSink> sinks(items.size());
+  for (size_t i = 0; i < items.size(); ++i) {
+    const FusedItem& it = items[i];
+    sar_status st = describe_reconstruct(*it.plan, it.pos, it.n_pos, it.n_pos, it.echo, it.scale, it.image,
+                                         it.workspace, sinks[i]);
+    if (st != SAR_OK) return st;
+  }
+  std::vector<Group> groups;
+  const size_t bytes = build_groups(sinks, groups);
+  if (bytes > capacity) {
+    // more launches than the table holds: run the items one after another
+    DirectSink direct(stream);
+    for (const FusedItem& it : items) {
+      sar_status st = describe_reconstruct(*it.plan, it.pos, it.n_pos, it.n_pos, it.echo, it.scale, it.image,
+                                           it.workspace, direct);
+      if (st != SAR_OK) return st;
+    }
+    return SAR_OK;
+  }
+  sar_status st = set_lds_attributes(groups);
+  if (st != SAR_OK) return st;
+  fill_blob(sinks, groups, h_table);
+  if ((st = check_hip(hipMemcpyAsync(d_table, h_table, bytes, hipMemcpyHostToDevice, stream), "table upload")) !=
+      SAR_OK)
+    return st;
+  return enqueue_groups(groups, d_table, stream);
+}
+
 }  // namespace sar

@@ -114,12 +114,29 @@ sar_status launch_fft_lines(const FftLines& a, LaunchSink& sink);
 sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, LaunchSink& sink);
 
 // whole per-scan pipeline on `stream` without stage timing (used by the server)
-sar_status reconstruct_on(Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
+sar_status reconstruct_on(const Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
                           void* d_image, void* d_workspace, hipStream_t stream);
 // whole per-scan pipeline described to a sink (used by fused batches)
 sar_status describe_reconstruct(const Plan& p, const double* d_pos, int64_t n_pos, int64_t n_pos_grid,
                                 const void* d_echo, float echo_scale, void* d_image, void* d_workspace,
                                 LaunchSink& sink);
+// One scan of a fused launch with its own workspace (device pointers).
+struct FusedItem {
+  const Plan* plan;
+  const double* pos;
+  int64_t n_pos;
+  const void* echo;
+  float scale;
+  void* image;
+  void* workspace;  // workspace_bytes(plan, n_pos), 256-byte aligned
+};
+// Runs the items' pipelines in fused launches on `stream`: their argument
+// tables are written to h_table (pinned, `capacity` bytes) and uploaded to
+// d_table on the stream; the caller keeps both until the launches have read
+// them (the upload is stream-ordered before the kernels).
+sar_status launch_fused(const std::vector<FusedItem>& items, char* d_table, char* h_table, size_t capacity,
+                        hipStream_t stream);
+
 // argument checks shared by sar_reconstruct and sar_submit (sets the error text)
 sar_status check_reconstruct_args(sar_plan plan, int64_t n_pos, const void* pos, const void* echo,
                                   const void* image);

@@ -2,14 +2,16 @@
 // (sar_server_* in include/sar.h).
 //
 // A server owns one device arena of the budgeted size, a small set of HIP
-// streams and a worker thread.  Submissions enter a FIFO queue; the worker
-// admits the head as soon as its memory (workspace, plus staging for host
-// inputs) fits in the arena and an in-flight slot is free, and queues the
-// scan's whole pipeline on the least-loaded stream.  Scans therefore overlap
-// on the device: a new scan starts while earlier ones are still running, and
-// small scans fill the compute units that one of them alone leaves idle.
-// Completion is signalled by a host callback queued behind the scan's last
-// kernel; it returns the scan's memory to the arena and wakes the worker.
+// streams and a worker thread.  Submissions enter a FIFO queue.  The worker
+// admits, in arrival order, every waiting scan whose memory (workspace, plus
+// staging for host inputs) fits in the arena, up to 16 at a time and 32 in
+// flight, and launches them as one unit on the least-loaded stream: a single
+// scan runs its own kernels, several scans run together in fused launches
+// (one grid per pipeline step holding the blocks of all of them).  Scans that
+// arrive while units are on the device form the next unit as soon as memory
+// and slots free up, and units on different streams overlap: continuous
+// batching.  Completion is signalled by a host callback queued behind a
+// unit's last kernel; it returns the unit's memory and wakes the worker.
 // Plans (geometry, sweep, grid tables, twiddles) stay resident: a request
 // only names one.
 #include <hip/hip_runtime.h>
@@ -33,7 +35,13 @@ namespace {
 using Clock = std::chrono::steady_clock;
 constexpr size_t kAlign = 256;
 constexpr int kStreams = 4;       // one per hardware queue of the default HIP setup
-constexpr int kMaxInFlight = 8;   // two scans queued per stream keeps each stream busy
+constexpr int kMaxInFlight = 32;  // scans admitted and not yet finished
+constexpr int kMaxUnit = 16;      // scans fused into one launch unit
+// scans whose workspace exceeds this fill the device on their own: they run
+// alone (unit of one) instead of holding up the small scans fused with them
+constexpr size_t kFuseMaxBytes = (size_t)512 << 20;
+constexpr int kSlots = 64;        // argument-table slots (>= units in flight)
+constexpr size_t kSlotBytes = 128 << 10;
 
 size_t round_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
@@ -84,6 +92,15 @@ class Arena {
 
 struct Request;
 
+// Scans launched together; `slot` holds their fused argument tables (-1: one
+// scan launched directly).
+struct Unit {
+  std::vector<Request*> reqs;
+  int stream = -1;
+  int slot = -1;
+  struct ServerState* srv = nullptr;
+};
+
 struct ServerState {
   int device = 0;
   size_t budget = 0;
@@ -91,6 +108,9 @@ struct ServerState {
   Arena arena;
   hipStream_t streams[kStreams] = {};
   int load[kStreams] = {};
+  char* h_tables = nullptr;  // pinned, kSlots x kSlotBytes
+  char* d_tables = nullptr;  // device, kSlots x kSlotBytes
+  std::vector<int> free_slots;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request*> queue;
@@ -113,7 +133,6 @@ struct Request {
   void* image = nullptr;
   size_t ws_bytes = 0, pos_bytes = 0, echo_bytes = 0, total = 0;
   size_t off = 0;
-  int stream = -1;
   Clock::time_point t_submit, t_done;
   bool done = false;
   sar_status status = SAR_OK;
@@ -122,52 +141,75 @@ struct Request {
 
 namespace {
 
-// Marks a request finished and returns its memory; called with the lock held.
-void finish_locked(ServerState& s, Request* r, sar_status st, const std::string& err) {
-  r->status = st;
-  r->error = err;
-  r->t_done = Clock::now();
-  r->done = true;
-  s.arena.release(r->off, r->total);
-  s.inflight -= 1;
-  s.load[r->stream] -= 1;
+// Marks a unit finished and returns its memory; called with the lock held.
+void finish_locked(ServerState& s, Unit* u, sar_status st, const std::string& err) {
+  const Clock::time_point now = Clock::now();
+  for (Request* r : u->reqs) {
+    r->status = st;
+    r->error = err;
+    r->t_done = now;
+    r->done = true;
+    s.arena.release(r->off, r->total);
+  }
+  s.inflight -= (int)u->reqs.size();
+  s.load[u->stream] -= 1;
+  if (u->slot >= 0) s.free_slots.push_back(u->slot);
+  delete u;
   s.cv.notify_all();
 }
 
-// Host callback queued behind a scan's last kernel (runs on a HIP runtime
+// Host callback queued behind a unit's last kernel (runs on a HIP runtime
 // thread; makes no HIP calls).
-void on_scan_done(void* arg) {
-  Request* r = (Request*)arg;
-  ServerState& s = *r->srv;
+void on_unit_done(void* arg) {
+  Unit* u = (Unit*)arg;
+  ServerState& s = *u->srv;
   std::lock_guard<std::mutex> lk(s.mu);
-  finish_locked(s, r, SAR_OK, std::string());
+  finish_locked(s, u, SAR_OK, std::string());
 }
 
-// Queues the copies (host inputs) and the pipeline of an admitted request.
-void launch(ServerState& s, Request* r) {
-  hipStream_t st = s.streams[r->stream];
-  char* base = s.pool + r->off;
-  const double* pos = r->pos;
-  const void* echo = r->echo;
+// Queues the copies (host inputs) and the pipelines of an admitted unit.
+void launch(ServerState& s, Unit* u) {
+  hipStream_t st = s.streams[u->stream];
+  std::vector<FusedItem> items;
   sar_status rc = SAR_OK;
-  if (!r->on_device && r->n_pos > 0) {
-    char* dpos = base + round_up(r->ws_bytes);
-    char* decho = dpos + round_up(r->pos_bytes);
-    rc = check_hip(hipMemcpyAsync(dpos, r->pos, r->pos_bytes, hipMemcpyHostToDevice, st), "position upload");
-    if (rc == SAR_OK)
-      rc = check_hip(hipMemcpyAsync(decho, r->echo, r->echo_bytes, hipMemcpyHostToDevice, st), "echo upload");
-    pos = (const double*)dpos;
-    echo = decho;
+  for (Request* r : u->reqs) {
+    char* base = s.pool + r->off;
+    const double* pos = r->pos;
+    const void* echo = r->echo;
+    if (!r->on_device && r->n_pos > 0) {
+      char* dpos = base + round_up(r->ws_bytes);
+      char* decho = dpos + round_up(r->pos_bytes);
+      if (rc == SAR_OK)
+        rc = check_hip(hipMemcpyAsync(dpos, r->pos, r->pos_bytes, hipMemcpyHostToDevice, st), "position upload");
+      if (rc == SAR_OK)
+        rc = check_hip(hipMemcpyAsync(decho, r->echo, r->echo_bytes, hipMemcpyHostToDevice, st), "echo upload");
+      pos = (const double*)dpos;
+      echo = decho;
+    }
+    items.push_back({&r->plan->p, pos, r->n_pos, echo, r->scale, r->image, base});
   }
-  if (rc == SAR_OK) rc = reconstruct_on(r->plan->p, pos, r->n_pos, echo, r->scale, r->image, base, st);
-  if (rc == SAR_OK) rc = check_hip(hipLaunchHostFunc(st, on_scan_done, r), "completion callback");
+  if (rc == SAR_OK) {
+    if (u->slot < 0) {
+      const FusedItem& it = items[0];
+      rc = reconstruct_on(*it.plan, it.pos, it.n_pos, it.echo, it.scale, it.image, it.workspace, st);
+    } else {
+      rc = launch_fused(items, s.d_tables + (size_t)u->slot * kSlotBytes, s.h_tables + (size_t)u->slot * kSlotBytes,
+                        kSlotBytes, st);
+    }
+  }
+  if (rc == SAR_OK) rc = check_hip(hipLaunchHostFunc(st, on_unit_done, u), "completion callback");
   if (rc != SAR_OK) {
     // work queued before the failure may still read the arena: drain the
     // stream before the memory is handed out again
     (void)hipStreamSynchronize(st);
     std::lock_guard<std::mutex> lk(s.mu);
-    finish_locked(s, r, rc, sar_last_error());
+    finish_locked(s, u, rc, sar_last_error());
   }
+}
+
+bool can_admit(const ServerState& s) {
+  return !s.queue.empty() && s.inflight < kMaxInFlight && !s.free_slots.empty() &&
+         s.arena.fits(s.queue.front()->total);
 }
 
 void worker_main(ServerState* sp) {
@@ -175,28 +217,35 @@ void worker_main(ServerState* sp) {
   (void)hipSetDevice(s.device);
   std::unique_lock<std::mutex> lk(s.mu);
   for (;;) {
-    s.cv.wait(lk, [&] {
-      if (s.stop && s.queue.empty() && s.inflight == 0) return true;
-      return !s.queue.empty() && s.inflight < kMaxInFlight && s.arena.fits(s.queue.front()->total);
-    });
+    s.cv.wait(lk, [&] { return (s.stop && s.queue.empty() && s.inflight == 0) || can_admit(s); });
     if (s.stop && s.queue.empty() && s.inflight == 0) break;
-    // admit in arrival order while memory and slots last
-    while (!s.queue.empty() && s.inflight < kMaxInFlight) {
+    // admit in arrival order while memory and slots last, into one unit
+    Unit* u = new Unit();
+    u->srv = &s;
+    while (!s.queue.empty() && s.inflight < kMaxInFlight && (int)u->reqs.size() < kMaxUnit) {
       Request* r = s.queue.front();
+      const bool large = r->ws_bytes > kFuseMaxBytes;
+      if (large && !u->reqs.empty()) break;
       size_t off = 0;
       if (!s.arena.alloc(r->total, &off)) break;
       s.queue.pop_front();
       r->off = off;
-      int best = 0;
-      for (int i = 1; i < kStreams; ++i)
-        if (s.load[i] < s.load[best]) best = i;
-      r->stream = best;
-      s.load[best] += 1;
+      u->reqs.push_back(r);
       s.inflight += 1;
-      lk.unlock();
-      launch(s, r);
-      lk.lock();
+      if (large) break;
     }
+    if (u->reqs.size() > 1) {
+      u->slot = s.free_slots.back();
+      s.free_slots.pop_back();
+    }
+    int best = 0;
+    for (int i = 1; i < kStreams; ++i)
+      if (s.load[i] < s.load[best]) best = i;
+    u->stream = best;
+    s.load[best] += 1;
+    lk.unlock();
+    launch(s, u);
+    lk.lock();
   }
 }
 
@@ -232,6 +281,15 @@ sar_status sar_server_create(int device, size_t hbm_budget_bytes, sar_server* ou
   }
   for (int i = 0; st == SAR_OK && i < kStreams; ++i)
     st = check_hip(hipStreamCreateWithFlags(&s.streams[i], hipStreamNonBlocking), "stream create");
+  if (st == SAR_OK && hipMalloc((void**)&s.d_tables, kSlots * kSlotBytes) != hipSuccess) {
+    s.d_tables = nullptr;
+    st = fail(SAR_ERR_NOMEM, "device argument tables");
+  }
+  if (st == SAR_OK && hipHostMalloc((void**)&s.h_tables, kSlots * kSlotBytes) != hipSuccess) {
+    s.h_tables = nullptr;
+    st = fail(SAR_ERR_NOMEM, "pinned argument tables");
+  }
+  for (int i = kSlots - 1; i >= 0; --i) s.free_slots.push_back(i);
   if (st == SAR_OK) {
     s.arena.reset(s.budget);
     try {
@@ -244,6 +302,8 @@ sar_status sar_server_create(int device, size_t hbm_budget_bytes, sar_server* ou
     for (auto& q : s.streams)
       if (q) (void)hipStreamDestroy(q);
     if (s.pool) (void)hipFree(s.pool);
+    if (s.d_tables) (void)hipFree(s.d_tables);
+    if (s.h_tables) (void)hipHostFree(s.h_tables);
     delete h;
   } else {
     *out = h;
@@ -340,6 +400,8 @@ sar_status sar_server_destroy(sar_server server) {
       (void)hipStreamDestroy(q);
     }
   if (s.pool) (void)hipFree(s.pool);
+  if (s.d_tables) (void)hipFree(s.d_tables);
+  if (s.h_tables) (void)hipHostFree(s.h_tables);
   for (auto& kv : s.reqs) delete kv.second;
   if (old >= 0 && old != s.device) (void)hipSetDevice(old);
   delete server;
