@@ -64,11 +64,14 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
   constexpr int L2 = MZ / kG;       // points per lane in the first FFT pass
   constexpr int WWIN = WZ + 2;      // register window of cells per lane
   static_assert(MZ % kG == 0 && MZ <= 1024, "Stolt grid of 64..1024 cells");
-  __shared__ float2 grid[kCols][MZ];
-  __shared__ float2 tw[MZ];
-  __shared__ float deap[1024];
-  for (int i = threadIdx.x; i < MZ; i += 64 * kWaves) tw[i] = a.tw[i];
-  for (int i = threadIdx.x; i < a.nz; i += 64 * kWaves) deap[i] = a.deapz[i];
+  // LDS row of one column: MZ cells, then read back as the [16][L2 + 1]
+  // padded transposition of the four-step FFT (one pad entry per row, so the
+  // 16 lanes of a column write to distinct banks); 4 more entries shift the
+  // rows of a wave's 4 columns onto different banks
+  constexpr int RS = kG * (L2 + 1) + 4;
+  __shared__ float2 grid[kCols][RS];
+  const float2* __restrict__ tw = a.tw;       // twiddles and deapodisation:
+  const float* __restrict__ deap = a.deapz;   // small tables, cached reads
   const int cl = threadIdx.x / kG;   // column slot in the block
   const int gl = threadIdx.x % kG;   // lane within the column's group
   float2* g = grid[cl];
@@ -148,7 +151,7 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
       constexpr int k2 = decltype(kc)::value;
       float2 y = v1[ct_bitrev(k2, ct_log2(L2))];
       if constexpr (k2 != 0) y = cmul(y, tw[gl * k2]);
-      g[gl * L2 + k2] = y;   // [l1][k2]
+      g[gl * (L2 + 1) + k2] = y;   // [l1][k2], padded rows
     });
     __syncthreads();
     if (live) {
@@ -157,7 +160,7 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
       for (int k2 = gl; k2 < L2; k2 += kG) {
         float2 v2[kG];
 #pragma unroll
-        for (int l1 = 0; l1 < kG; ++l1) v2[l1] = g[l1 * L2 + k2];
+        for (int l1 = 0; l1 < kG; ++l1) v2[l1] = g[l1 * (L2 + 1) + k2];
         reg_dft_dif<kG, +1>(v2);
         static_for<0, kG>([&](auto kc) __attribute__((always_inline)) {
           constexpr int k1 = decltype(kc)::value;
