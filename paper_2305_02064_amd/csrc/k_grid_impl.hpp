@@ -48,7 +48,8 @@ namespace grid_impl {
 
 constexpr int TX = kTileX;
 constexpr int TY = kTileY;
-constexpr int FPL = 2;  // frequencies per lane
+constexpr int FPL = 2;     // frequencies per lane
+constexpr int kChunk = 6;  // samples per pipeline chunk (two chunk buffers per wave)
 
 struct GridArgs {
   const void* rec;
@@ -83,6 +84,9 @@ template <int W, int ET>
 struct GridBody {
   using Args = GridArgs;
   static constexpr int kThreads = 64;
+  // three waves per SIMD (<= 168 registers) hide the LDS and memory latency;
+  // wider kernels need more registers for their weights
+  static constexpr int kMinWavesPerEU = W <= 4 ? 3 : 2;
   static __device__ __forceinline__ void run(const GridArgs& a, uint32_t blk, uint32_t nblk);
 };
 
@@ -91,13 +95,17 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
   constexpr int NBX = TX + W - 1;     // last-tap column offsets touching a tile
   constexpr int NBY = TY + W - 1;     // last-tap row offsets touching a tile
   constexpr int NSEG = 2 * NBY;       // each row of cells may split at the x wrap
-  constexpr int CH = 8;               // samples per pipeline chunk
-  constexpr int EBH = ET == SAR_ECHO_C64 ? 512 : 256;  // echo bytes per sample, per 64 frequencies
-  constexpr int EB = FPL * EBH;
+  constexpr int CH = kChunk;          // samples per pipeline chunk
+  constexpr int EBH = 512;            // bytes per sample and 64 frequencies of compensated values
+  constexpr int EB = FPL * EBH;       // bytes per sample of one chunk buffer
+  constexpr int NW = 2 * W;           // weight words per sample (wx then wy)
+  constexpr int WS = (NW + 3) / 4 * 4;      // padded to 16-byte blocks for 128-bit reads
+  constexpr int NWQ = (CH * WS + 63) / 64;  // weight loads per chunk (64 words each)
+  constexpr int BUF = CH * EB + NWQ * 256;  // one chunk buffer: values, then weights
   static_assert(NBY * NBX <= 192, "pattern chain covers 192 patterns");
   __shared__ int seg_s[NSEG];
   __shared__ int seg_off[NSEG + 1];
-  __shared__ __attribute__((aligned(16))) char echobuf[CH * EB];
+  __shared__ __attribute__((aligned(16))) char cbuf[2][BUF];
 
   // row-major tile order (x fastest, frequency chunk slowest); measured
   // faster than narrower strip orders for the serpentine scans
@@ -172,11 +180,17 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
     const int bb = ((int)(cxy & 0xffffu) - tx0) & (a.mx - 1);  // last-tap column offset in [0, NBX)
     return aa * NBX + bb;
   };
-  // echo rows of a chunk into LDS with direct global-to-LDS loads; 16-byte
-  // loads need every complex pair (2 frequencies) to lie inside the row
+  // Chunk c into buffer b with direct global-to-LDS loads: the echo rows of
+  // its samples (frequency-major, compensated in place later) and their
+  // kernel weights (lane L loads word L % WS of the chunk's sample L / WS;
+  // words NW..WS-1 are padding).
+  // 16-byte echo loads need every complex pair (2 frequencies) inside the row.
+  constexpr int RF = (int)(sizeof(SampleRec<W>) / 4);           // record size in words
+  constexpr int WOFF = (int)(offsetof(SampleRec<W>, wx) / 4);   // first weight word
   const bool quad_ok = (a.nf & 1) == 0;
-  auto stage_echo = [&](int c, int srcv) __attribute__((always_inline)) {
+  auto stage = [&](int c, int b, int srcv, int sidxv) __attribute__((always_inline)) {
     const int n = min(CH, total - c * CH);
+    char* buf = cbuf[b];
     for (int k = 0; k < n; ++k) {
       const int src = __builtin_amdgcn_readlane(srcv, k);
       if constexpr (ET == SAR_ECHO_C64) {
@@ -184,41 +198,33 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
         if (quad_ok) {
           // one 16-byte load per lane covers the 128 frequencies (2 per lane)
           const int fi = fbase * 2 + 4 * lane;
-          dma_quad(row + (fi < 2 * a.nf ? fi : 0), echobuf + k * EB);
+          dma_quad(row + (fi < 2 * a.nf ? fi : 0), buf + k * EB);
         } else {
 #pragma unroll
           for (int q = 0; q < 2 * FPL; ++q) {
             const int fi = fbase * 2 + q * 64 + lane;   // float index within the row
-            dma_dword(row + (fi < 2 * a.nf ? fi : 0), echobuf + k * EB + q * 256);
+            dma_dword(row + (fi < 2 * a.nf ? fi : 0), buf + k * EB + q * 256);
           }
         }
       } else {
+        // half pairs land in the first half of the sample's slot
         const uint32_t* row = (const uint32_t*)a.echo + (int64_t)src * a.nf;
 #pragma unroll
         for (int q = 0; q < FPL; ++q) {
           const int fi = fbase + q * 64 + lane;
-          dma_dword(row + (fi < a.nf ? fi : 0), echobuf + k * EB + q * 256);
+          dma_dword(row + (fi < a.nf ? fi : 0), buf + k * EB + q * 256);
         }
       }
     }
-  };
-  // kernel weights of one sample through scalar loads
-  typedef const __attribute__((address_space(4))) float* cfloat_ptr;
-  const cfloat_ptr cw = (cfloat_ptr)a.rec;
-  constexpr int RF = (int)(sizeof(SampleRec<W>) / 4);           // record size in words
-  constexpr int WOFF = (int)(offsetof(SampleRec<W>, wx) / 4);   // first weight word
-  struct Weights {
-    float wx[W], wy[W];
-  };
-  auto load_weights = [&](int sidx) __attribute__((always_inline)) {
-    const cfloat_ptr p = cw + (int64_t)sidx * RF + WOFF;
-    Weights out;
 #pragma unroll
-    for (int q = 0; q < W; ++q) {
-      out.wx[q] = p[q];
-      out.wy[q] = p[W + q];
+    for (int q = 0; q < NWQ; ++q) {
+      const int L = q * 64 + lane;
+      const int k = L / WS;
+      const int wd = L - k * WS;
+      const int si = __shfl(sidxv, k < n ? k : 0);   // a sample of this chunk
+      const float* src = (const float*)a.rec + (int64_t)si * RF + WOFF + (wd < NW ? wd : 0);
+      dma_dword(src, buf + CH * EB + q * 256);
     }
-    return out;
   };
 
   float2 acc[TY][TX][FPL];
@@ -229,77 +235,115 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
 #pragma unroll
       for (int h = 0; h < FPL; ++h) acc[r][c][h] = make_float2(0.f, 0.f);
 
-  // pipeline: while chunk c is processed from registers, the echo rows of
-  // chunk c+1, the residual paths and offsets of chunk c+1 and the source rows
-  // of chunk c+2 are in flight
+  // pipeline: while chunk c is processed from buffer c & 1, the echo rows and
+  // weights of chunk c+1 fill the other buffer, and the residual paths,
+  // patterns and source rows of the chunks after are gathered
   int sidx0 = chunk_index(0);
   int sidx1 = chunk_index(1);
   double beta0 = gather_beta(sidx0);
   int idx0 = gather_idx(sidx0);
   int src1 = sidx1 >= 0 ? a.order[sidx1] : 0;
-  if (nchunk > 0) stage_echo(0, sidx0 >= 0 ? a.order[sidx0] : 0);
-  typedef float evec __attribute__((ext_vector_type(2 * FPL * CH)));
+  if (nchunk > 0) stage(0, 0, sidx0 >= 0 ? a.order[sidx0] : 0, sidx0);
   for (int c = 0; c < nchunk; ++c) {
+    char* buf = cbuf[c & 1];
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const int n = __builtin_amdgcn_readfirstlane(min(CH, total - c * CH));
-    // the chunk's compensated values in one register vector: [sample][freq][re, im]
+    // compensation in place, one sample at a time:
     // s_hat = s exp(+j 2 pi f beta / c), k * beta in float64 reduced modulo a cycle
-    evec ev;
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
+    for (int k = 0; k < n; ++k) {
       const double bk = readlane_f64(beta0, k);
+      float2 t2[FPL];
 #pragma unroll
       for (int h = 0; h < FPL; ++h) {
-        float2 t2;
         if constexpr (ET == SAR_ECHO_C64) {
-          t2 = *(const float2*)(echobuf + k * EB + h * EBH + lane * 8);
+          t2[h] = *(const float2*)(buf + k * EB + h * EBH + lane * 8);
         } else {
-          t2 = __half22float2(*(const __half2*)(echobuf + k * EB + h * EBH + lane * 4));
-          t2 = make_float2(t2.x * a.echo_scale, t2.y * a.echo_scale);
+          const float2 u = __half22float2(*(const __half2*)(buf + k * EB + h * 256 + lane * 4));
+          t2[h] = make_float2(u.x * a.echo_scale, u.y * a.echo_scale);
         }
-        const float2 v = cmul(t2, cis_cycles(bk * fcc[h]));
-        ev[(k * FPL + h) * 2] = v.x;
-        ev[(k * FPL + h) * 2 + 1] = v.y;
       }
+#pragma unroll
+      for (int h = 0; h < FPL; ++h)
+        *(float2*)(buf + k * EB + h * EBH + lane * 8) = cmul(t2[h], cis_cycles(bk * fcc[h]));
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (c + 1 < nchunk) stage_echo(c + 1, src1);
+    if (c + 1 < nchunk) stage(c + 1, (c + 1) & 1, src1, sidx1);
     const int sidx2 = chunk_index(c + 2);
     const int src2 = sidx2 >= 0 ? a.order[sidx2] : 0;
     const double beta1 = gather_beta(sidx1);
     const int idx1 = gather_idx(sidx1);
-    Weights wt = load_weights(__builtin_amdgcn_readlane(sidx0, 0));
     // one sample with its tap pattern fixed at compile time: I = row offset *
     // NBX + column offset of its last tap relative to the tile
     int k = 0;
+    // LDS addresses (32-bit) of this lane's values and of the weights
+    typedef __attribute__((address_space(3))) char lds_char;
+    const uint32_t vbase = (uint32_t)(uintptr_t)(lds_char*)buf + 8u * (uint32_t)lane;
+    const uint32_t wbase = (uint32_t)(uintptr_t)(lds_char*)(buf + CH * EB);
     auto visit = [&](auto ic) __attribute__((always_inline)) {
       constexpr int I = decltype(ic)::value;
       constexpr int AA = I / NBX - (W - 1);   // first-tap row offset
       constexpr int BB = I % NBX - (W - 1);   // first-tap column offset
-      const Weights wc = wt;
-      // scalar loads return out of order and can only be waited for all
-      // together: issue the next sample's load only after the current one
-      // has been consumed
-      asm volatile("" ::: "memory");
-      if (k + 1 < n) wt = load_weights(__builtin_amdgcn_readlane(sidx0, k + 1));
-      float2 v[FPL];
+      // The sample's two compensated values and its weights, read and
+      // waited for in one block: the next chunk's direct loads into the other
+      // buffer stay in flight (a compiler-visible LDS read would wait for them).
+      typedef float f2v __attribute__((ext_vector_type(2)));
+      typedef float f4v __attribute__((ext_vector_type(4)));
+      f2v r0, r1;
+      f4v q0, q1, q2 = {0.f, 0.f, 0.f, 0.f}, q3 = {0.f, 0.f, 0.f, 0.f};
+      const uint32_t va = vbase + (uint32_t)(k * EB);
+      const uint32_t wa = wbase + (uint32_t)(k * WS * 4);
+      static_assert(EBH == 512 && FPL == 2, "value offsets in the read block");
+      if constexpr (WS == 8) {
+        asm volatile(
+            "ds_read_b64 %0, %4\n\tds_read_b64 %1, %4 offset:512\n\t"
+            "ds_read_b128 %2, %5\n\tds_read_b128 %3, %5 offset:16\n\ts_waitcnt lgkmcnt(0)"
+            : "=&v"(r0), "=&v"(r1), "=&v"(q0), "=&v"(q1)
+            : "v"(va), "v"(wa)
+            : "memory");
+      } else if constexpr (WS == 12) {
+        asm volatile(
+            "ds_read_b64 %0, %5\n\tds_read_b64 %1, %5 offset:512\n\t"
+            "ds_read_b128 %2, %6\n\tds_read_b128 %3, %6 offset:16\n\tds_read_b128 %4, %6 offset:32\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(r0), "=&v"(r1), "=&v"(q0), "=&v"(q1), "=&v"(q2)
+            : "v"(va), "v"(wa)
+            : "memory");
+      } else {
+        static_assert(WS == 16, "weight block of 8, 12 or 16 words");
+        asm volatile(
+            "ds_read_b64 %0, %6\n\tds_read_b64 %1, %6 offset:512\n\t"
+            "ds_read_b128 %2, %7\n\tds_read_b128 %3, %7 offset:16\n\t"
+            "ds_read_b128 %4, %7 offset:32\n\tds_read_b128 %5, %7 offset:48\n\ts_waitcnt lgkmcnt(0)"
+            : "=&v"(r0), "=&v"(r1), "=&v"(q0), "=&v"(q1), "=&v"(q2), "=&v"(q3)
+            : "v"(va), "v"(wa)
+            : "memory");
+      }
+      float wv[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                      q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+      float wx[W], wy[W];
 #pragma unroll
-      for (int h = 0; h < FPL; ++h) v[h] = make_float2(ev[(k * FPL + h) * 2], ev[(k * FPL + h) * 2 + 1]);
+      for (int q = 0; q < W; ++q) {
+        wx[q] = wv[q];
+        wy[q] = wv[W + q];
+      }
+      float2 v[FPL];
+      v[0] = make_float2(r0.x, r0.y);
+      v[1] = make_float2(r1.x, r1.y);
       static_for<0, W>([&](auto jc) __attribute__((always_inline)) {
         constexpr int jj = decltype(jc)::value;
         constexpr int rr = AA + jj;
         if constexpr (rr >= 0 && rr < TY) {
           float2 vy[FPL];
 #pragma unroll
-          for (int h = 0; h < FPL; ++h) vy[h] = cscale(v[h], wc.wy[jj]);
+          for (int h = 0; h < FPL; ++h) vy[h] = cscale(v[h], wy[jj]);
           static_for<0, W>([&](auto kc) __attribute__((always_inline)) {
             constexpr int kk = decltype(kc)::value;
             constexpr int cc = BB + kk;
             if constexpr (cc >= 0 && cc < TX) {
 #pragma unroll
-              for (int h = 0; h < FPL; ++h) cfma(acc[rr][cc][h], vy[h], wc.wx[kk]);
+              for (int h = 0; h < FPL; ++h) cfma(acc[rr][cc][h], vy[h], wx[kk]);
             }
           });
         }
@@ -333,7 +377,6 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
       if (cur < 0 || cur >= NBY * NBX) {
         if (++k >= n) break;
         cur = __builtin_amdgcn_readlane(idx0, k);
-        wt = load_weights(__builtin_amdgcn_readlane(sidx0, k));
       }
     }
   chunk_done:

@@ -31,14 +31,25 @@ struct BatchItem {
   uint32_t count;  // blocks of the item
 };
 
+// Minimum waves per SIMD a body asks the register allocator for (default 1).
+template <class Body, class = void>
+struct MinWaves {
+  static constexpr int value = 1;
+};
 template <class Body>
-__global__ __launch_bounds__(Body::kThreads) void k_single(typename Body::Args a) {
+struct MinWaves<Body, decltype((void)Body::kMinWavesPerEU)> {
+  static constexpr int value = Body::kMinWavesPerEU;
+};
+
+template <class Body>
+__global__ __launch_bounds__(Body::kThreads) __attribute__((amdgpu_waves_per_eu(MinWaves<Body>::value)))
+void k_single(typename Body::Args a) {
   Body::run(a, blockIdx.x, gridDim.x);
 }
 
 template <class Body>
-__global__ __launch_bounds__(Body::kThreads) void k_batch(const typename Body::Args* __restrict__ args,
-                                                          const BatchItem* __restrict__ items, int n) {
+__global__ __launch_bounds__(Body::kThreads) __attribute__((amdgpu_waves_per_eu(MinWaves<Body>::value)))
+void k_batch(const typename Body::Args* __restrict__ args, const BatchItem* __restrict__ items, int n) {
   const uint32_t b = blockIdx.x;
   int lo = 0, hi = n;  // last item whose first block is <= b
   while (hi - lo > 1) {
