@@ -25,7 +25,7 @@ __device__ __forceinline__ void cfma(float2& a, float2 b, float s) {
 // exp(j 2 pi t) for t given in cycles (float64); the fractional part is taken
 // in float64, then the hardware sine/cosine (which take revolutions) run on it.
 __device__ __forceinline__ float2 cis_cycles(double t) {
-  const double fr = t - floor(t);
+  const double fr = __builtin_amdgcn_fract(t);  // t - floor(t) in one instruction
   const float r = (float)fr;
   return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
 }

@@ -249,23 +249,33 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const int n = __builtin_amdgcn_readfirstlane(min(CH, total - c * CH));
-    // compensation in place, one sample at a time:
-    // s_hat = s exp(+j 2 pi f beta / c), k * beta in float64 reduced modulo a cycle
-    for (int k = 0; k < n; ++k) {
-      const double bk = readlane_f64(beta0, k);
-      float2 t2[FPL];
+    // compensation in place, two samples at a time (chunks hold an even
+    // number of slots; a spare slot is processed but never read):
+    // s_hat = s exp(+j 2 pi f beta / c), k * beta in float64 reduced modulo a
+    // cycle, then hardware sine and cosine (which overlap the other vector
+    // work, so every frequency takes its own phase)
+    static_assert(CH % 2 == 0, "compensation pairs");
+    for (int k = 0; k < n; k += 2) {
+      float2 t2[2][FPL];
+      double bk[2];
 #pragma unroll
-      for (int h = 0; h < FPL; ++h) {
-        if constexpr (ET == SAR_ECHO_C64) {
-          t2[h] = *(const float2*)(buf + k * EB + h * EBH + lane * 8);
-        } else {
-          const float2 u = __half22float2(*(const __half2*)(buf + k * EB + h * 256 + lane * 4));
-          t2[h] = make_float2(u.x * a.echo_scale, u.y * a.echo_scale);
+      for (int u = 0; u < 2; ++u) {
+        bk[u] = readlane_f64(beta0, k + u);
+#pragma unroll
+        for (int h = 0; h < FPL; ++h) {
+          if constexpr (ET == SAR_ECHO_C64) {
+            t2[u][h] = *(const float2*)(buf + (k + u) * EB + h * EBH + lane * 8);
+          } else {
+            const float2 w2 = __half22float2(*(const __half2*)(buf + (k + u) * EB + h * 256 + lane * 4));
+            t2[u][h] = make_float2(w2.x * a.echo_scale, w2.y * a.echo_scale);
+          }
         }
       }
 #pragma unroll
-      for (int h = 0; h < FPL; ++h)
-        *(float2*)(buf + k * EB + h * EBH + lane * 8) = cmul(t2[h], cis_cycles(bk * fcc[h]));
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int h = 0; h < FPL; ++h)
+          *(float2*)(buf + (k + u) * EB + h * EBH + lane * 8) = cmul(t2[u][h], cis_cycles(bk[u] * fcc[h]));
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
