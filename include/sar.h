@@ -121,6 +121,9 @@ typedef struct {
   int32_t n_pair;        /* n_tx * n_rx */
   int32_t n_stages;      /* entries returned by sar_plan_stage_times */
   size_t workspace_bytes_max; /* workspace for n_pos = max_pos */
+  int32_t grid_tile;     /* gridding tile configuration in use (see sar_plan_autotune) */
+  int32_t grid_tile_x, grid_tile_y;  /* its cells per wave along x and y */
+  int32_t grid_freqs_per_lane;       /* its frequencies per lane (64 lanes per wave) */
 } sar_plan_info;
 
 /* Create a plan on HIP device `device`: validates the descriptor, chooses the
@@ -162,6 +165,23 @@ sar_status sar_spectrum(sar_plan plan, const double* d_pos, int64_t n_pos, const
  * output).  d_workspace needs sar_plan_workspace_bytes(plan, 0) bytes. */
 sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* d_image, void* d_workspace,
                                    sar_stream_t stream);
+
+/* Autotuner: times every compiled gridding tile configuration (8 x 4 cells
+ * with 2 frequencies per lane; 8 x 8 cells with 1 frequency per lane, built
+ * for kernels of up to 6 taps) on the given scan, which should be
+ * representative of the plan's workload, and keeps the fastest for every
+ * later call of this plan.  Runs a0-a2 a few times on `stream` and waits for
+ * them (synchronous).  The default before tuning: 1 frequency per lane when
+ * the sweep has at most 64 frequencies, else 2.  Tune before creating
+ * batches from the plan and not while other calls use it.  tile_out (may be
+ * NULL) receives the chosen configuration.  Arguments as sar_reconstruct. */
+sar_status sar_plan_autotune(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,
+                             float echo_scale, void* d_workspace, sar_stream_t stream, int32_t* tile_out);
+
+/* Select a gridding tile configuration directly (0 or 1, as listed for
+ * sar_plan_autotune).  SAR_ERR_UNSUPPORTED if it is not compiled for the
+ * plan's kernel width; same restrictions as sar_plan_autotune. */
+sar_status sar_plan_set_grid_tile(sar_plan plan, int32_t tile);
 
 /* Per-stage timing with HIP events recorded on the call's stream around each
  * kernel group (stage order: 0 geometry+sort, 1 gridding, 2 FFT along x,

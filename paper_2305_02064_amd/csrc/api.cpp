@@ -259,7 +259,66 @@ sar_status sar_plan_get_info(sar_plan plan, sar_plan_info* info) {
   info->n_pair = p.n_pair;
   info->n_stages = kNumStages;
   info->workspace_bytes_max = workspace_bytes(p, p.max_pos, nullptr, nullptr);
+  info->grid_tile = p.grid_tile;
+  info->grid_tile_x = kGridTiles[p.grid_tile][0];
+  info->grid_tile_y = kGridTiles[p.grid_tile][1];
+  info->grid_freqs_per_lane = kGridTiles[p.grid_tile][2];
   return SAR_OK;
+}
+
+sar_status sar_plan_set_grid_tile(sar_plan plan, int32_t tile) {
+  if (!plan) return fail(SAR_ERR_INVALID, "plan is NULL");
+  if (tile < 0 || tile >= kNumGridTiles) return fail(SAR_ERR_INVALID, "no such gridding tile configuration");
+  if (plan->p.w > kGridTileMaxWidth[tile])
+    return fail(SAR_ERR_UNSUPPORTED, "gridding tile " + std::to_string(tile) + " is compiled for kernels of up to " +
+                                         std::to_string(kGridTileMaxWidth[tile]) + " taps");
+  plan->p.grid_tile = tile;
+  return SAR_OK;
+}
+
+sar_status sar_plan_autotune(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
+                             void* d_workspace, sar_stream_t stream, int32_t* tile_out) {
+  sar_status st = check_call(plan, n_pos, d_pos, d_echo, d_workspace, d_workspace);
+  if (st != SAR_OK) return st;
+  Plan& p = plan->p;
+  DeviceGuard g(p.device);
+  hipStream_t s = (hipStream_t)stream;
+  Workspace ws;
+  workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
+  DirectSink sink(s);
+  if ((st = launch_geometry_sort(p, d_pos, n_pos, n_pos, ws, sink)) != SAR_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if ((st = check_hip(hipEventCreate(&e0), "event create")) != SAR_OK) return st;
+  if ((st = check_hip(hipEventCreate(&e1), "event create")) != SAR_OK) {
+    (void)hipEventDestroy(e0);
+    return st;
+  }
+  const int old_tile = p.grid_tile;
+  int best = old_tile;
+  float best_ms = 0.f;
+  for (int t = 0; t < kNumGridTiles && st == SAR_OK; ++t) {
+    if (p.w > kGridTileMaxWidth[t]) continue;
+    p.grid_tile = t;
+    float t_min = 0.f;
+    for (int rep = 0; rep < 4 && st == SAR_OK; ++rep) {  // first run warms up
+      st = check_hip(hipEventRecord(e0, s), "event record");
+      if (st == SAR_OK) st = launch_gridding(p, d_echo, echo_scale, ws, ws.region_a, sink);
+      if (st == SAR_OK) st = check_hip(hipEventRecord(e1, s), "event record");
+      if (st == SAR_OK) st = check_hip(hipEventSynchronize(e1), "event wait");
+      float ms = 0.f;
+      if (st == SAR_OK) st = check_hip(hipEventElapsedTime(&ms, e0, e1), "event time");
+      if (st == SAR_OK && rep > 0 && (rep == 1 || ms < t_min)) t_min = ms;
+    }
+    if (st == SAR_OK && (best_ms == 0.f || t_min < best_ms)) {
+      best_ms = t_min;
+      best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p.grid_tile = st == SAR_OK ? best : old_tile;
+  if (tile_out) *tile_out = p.grid_tile;
+  return st;
 }
 
 sar_status sar_reconstruct(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,

@@ -36,19 +36,36 @@
 #include "launch.hpp"
 #include "sar_internal.hpp"
 
-// Repeats M(I) for I = 0 .. 191 (covers NBY * NBX up to (4 + 7) * (8 + 7) = 165).
+// Repeats M(I) for I = 0 .. 255 (covers NBY * NBX up to (4 + 7) * (8 + 7) = 165
+// for 8 x 4 tiles and (8 + 5) * (8 + 5) = 169 for 8 x 8 tiles up to 6 taps).
 #define SAR_GRID_R4(M, B) M((B)) M((B) + 1) M((B) + 2) M((B) + 3)
 #define SAR_GRID_R16(M, B) SAR_GRID_R4(M, B) SAR_GRID_R4(M, (B) + 4) SAR_GRID_R4(M, (B) + 8) SAR_GRID_R4(M, (B) + 12)
 #define SAR_GRID_R64(M, B) \
   SAR_GRID_R16(M, B) SAR_GRID_R16(M, (B) + 16) SAR_GRID_R16(M, (B) + 32) SAR_GRID_R16(M, (B) + 48)
-#define SAR_GRID_CASES(M) SAR_GRID_R64(M, 0) SAR_GRID_R64(M, 64) SAR_GRID_R64(M, 128)
+#define SAR_GRID_CASES(M) SAR_GRID_R64(M, 0) SAR_GRID_R64(M, 64) SAR_GRID_R64(M, 128) SAR_GRID_R64(M, 192)
 
 namespace sar {
 namespace grid_impl {
 
-constexpr int TX = kTileX;
-constexpr int TY = kTileY;
-constexpr int FPL = 2;     // frequencies per lane
+// Tile configurations: TX x TY cells per wave, FPL frequencies per lane
+// (64 * FPL per wave); both keep 2 * TX * TY * FPL = 128 accumulator
+// registers.  0: 8 x 4 cells, 2 frequencies (fewer sample visits per
+// frequency); 1: 8 x 8 cells, 1 frequency (less halo, and no idle lanes when
+// a sweep has at most 64 frequencies).
+template <int TC>
+struct TileCfg;
+template <>
+struct TileCfg<0> {
+  static constexpr int TX = 8, TY = 4, FPL = 2;
+};
+template <>
+struct TileCfg<1> {
+  static constexpr int TX = 8, TY = 8, FPL = 1;
+};
+static_assert(TileCfg<0>::TX == kGridTiles[0][0] && TileCfg<0>::TY == kGridTiles[0][1] &&
+                  TileCfg<0>::FPL == kGridTiles[0][2] && TileCfg<1>::TX == kGridTiles[1][0] &&
+                  TileCfg<1>::TY == kGridTiles[1][1] && TileCfg<1>::FPL == kGridTiles[1][2],
+              "host table of tile configurations");
 constexpr int kChunk = 6;  // samples per pipeline chunk (two chunk buffers per wave)
 
 struct GridArgs {
@@ -80,7 +97,7 @@ __device__ __forceinline__ void dma_quad(const void* src, void* lds_base) {
   __builtin_amdgcn_global_load_lds(src, (void __attribute__((address_space(3)))*)lds_base, 16, 0, 0);
 }
 
-template <int W, int ET>
+template <int W, int ET, int TC>
 struct GridBody {
   using Args = GridArgs;
   static constexpr int kThreads = 64;
@@ -90,8 +107,11 @@ struct GridBody {
   static __device__ __forceinline__ void run(const GridArgs& a, uint32_t blk, uint32_t nblk);
 };
 
-template <int W, int ET>
-__device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t blk, uint32_t nblk) {
+template <int W, int ET, int TC>
+__device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint32_t blk, uint32_t nblk) {
+  constexpr int TX = TileCfg<TC>::TX;
+  constexpr int TY = TileCfg<TC>::TY;
+  constexpr int FPL = TileCfg<TC>::FPL;
   constexpr int NBX = TX + W - 1;     // last-tap column offsets touching a tile
   constexpr int NBY = TY + W - 1;     // last-tap row offsets touching a tile
   constexpr int NSEG = 2 * NBY;       // each row of cells may split at the x wrap
@@ -102,7 +122,7 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
   constexpr int WS = (NW + 3) / 4 * 4;      // padded to 16-byte blocks for 128-bit reads
   constexpr int NWQ = (CH * WS + 63) / 64;  // weight loads per chunk (64 words each)
   constexpr int BUF = CH * EB + NWQ * 256;  // one chunk buffer: values, then weights
-  static_assert(NBY * NBX <= 192, "pattern chain covers 192 patterns");
+  static_assert(NBY * NBX <= 256, "pattern chain covers 256 patterns");
   __shared__ int seg_s[NSEG];
   __shared__ int seg_off[NSEG + 1];
   __shared__ __attribute__((aligned(16))) char cbuf[2][BUF];
@@ -195,7 +215,7 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
       const int src = __builtin_amdgcn_readlane(srcv, k);
       if constexpr (ET == SAR_ECHO_C64) {
         const float* row = (const float*)a.echo + (int64_t)src * a.nf * 2;
-        if (quad_ok) {
+        if (FPL == 2 && quad_ok) {
           // one 16-byte load per lane covers the 128 frequencies (2 per lane)
           const int fi = fbase * 2 + 4 * lane;
           dma_quad(row + (fi < 2 * a.nf ? fi : 0), buf + k * EB);
@@ -300,19 +320,19 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
       // buffer stay in flight (a compiler-visible LDS read would wait for them).
       typedef float f2v __attribute__((ext_vector_type(2)));
       typedef float f4v __attribute__((ext_vector_type(4)));
-      f2v r0, r1;
+      f2v r0, r1 = {0.f, 0.f};
       f4v q0, q1, q2 = {0.f, 0.f, 0.f, 0.f}, q3 = {0.f, 0.f, 0.f, 0.f};
       const uint32_t va = vbase + (uint32_t)(k * EB);
       const uint32_t wa = wbase + (uint32_t)(k * WS * 4);
-      static_assert(EBH == 512 && FPL == 2, "value offsets in the read block");
-      if constexpr (WS == 8) {
+      static_assert(EBH == 512, "value offsets in the read block");
+      if constexpr (FPL == 2 && WS == 8) {
         asm volatile(
             "ds_read_b64 %0, %4\n\tds_read_b64 %1, %4 offset:512\n\t"
             "ds_read_b128 %2, %5\n\tds_read_b128 %3, %5 offset:16\n\ts_waitcnt lgkmcnt(0)"
             : "=&v"(r0), "=&v"(r1), "=&v"(q0), "=&v"(q1)
             : "v"(va), "v"(wa)
             : "memory");
-      } else if constexpr (WS == 12) {
+      } else if constexpr (FPL == 2 && WS == 12) {
         asm volatile(
             "ds_read_b64 %0, %5\n\tds_read_b64 %1, %5 offset:512\n\t"
             "ds_read_b128 %2, %6\n\tds_read_b128 %3, %6 offset:16\n\tds_read_b128 %4, %6 offset:32\n\t"
@@ -320,13 +340,29 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
             : "=&v"(r0), "=&v"(r1), "=&v"(q0), "=&v"(q1), "=&v"(q2)
             : "v"(va), "v"(wa)
             : "memory");
-      } else {
+      } else if constexpr (FPL == 2) {
         static_assert(WS == 16, "weight block of 8, 12 or 16 words");
         asm volatile(
             "ds_read_b64 %0, %6\n\tds_read_b64 %1, %6 offset:512\n\t"
             "ds_read_b128 %2, %7\n\tds_read_b128 %3, %7 offset:16\n\t"
             "ds_read_b128 %4, %7 offset:32\n\tds_read_b128 %5, %7 offset:48\n\ts_waitcnt lgkmcnt(0)"
             : "=&v"(r0), "=&v"(r1), "=&v"(q0), "=&v"(q1), "=&v"(q2), "=&v"(q3)
+            : "v"(va), "v"(wa)
+            : "memory");
+      } else if constexpr (WS == 8) {
+        static_assert(FPL == 1, "one or two frequencies per lane");
+        asm volatile(
+            "ds_read_b64 %0, %3\n\tds_read_b128 %1, %4\n\tds_read_b128 %2, %4 offset:16\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(r0), "=&v"(q0), "=&v"(q1)
+            : "v"(va), "v"(wa)
+            : "memory");
+      } else {
+        static_assert(FPL == 1 && WS == 12, "one-frequency tiles are built for kernels of 3 to 6 taps");
+        asm volatile(
+            "ds_read_b64 %0, %4\n\tds_read_b128 %1, %5\n\tds_read_b128 %2, %5 offset:16\n\t"
+            "ds_read_b128 %3, %5 offset:32\n\ts_waitcnt lgkmcnt(0)"
+            : "=&v"(r0), "=&v"(q0), "=&v"(q1), "=&v"(q2)
             : "v"(va), "v"(wa)
             : "memory");
       }
@@ -340,7 +376,7 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
       }
       float2 v[FPL];
       v[0] = make_float2(r0.x, r0.y);
-      v[1] = make_float2(r1.x, r1.y);
+      if constexpr (FPL == 2) v[1] = make_float2(r1.x, r1.y);
       static_for<0, W>([&](auto jc) __attribute__((always_inline)) {
         constexpr int jj = decltype(jc)::value;
         constexpr int rr = AA + jj;
@@ -409,9 +445,12 @@ __device__ __forceinline__ void GridBody<W, ET>::run(const GridArgs& a, uint32_t
   }
 }
 
-template <int W>
+template <int W, int TC>
 sar_status grid_w(const Plan& p, const void* d_echo, float echo_scale, const Workspace& ws, float2* grid,
                   LaunchSink& sink) {
+  constexpr int TX = TileCfg<TC>::TX;
+  constexpr int TY = TileCfg<TC>::TY;
+  constexpr int FPL = TileCfg<TC>::FPL;
   GridArgs a;
   a.rec = ws.rec;
   a.cell_start = ws.cell_start;
@@ -427,16 +466,21 @@ sar_status grid_w(const Plan& p, const void* d_echo, float echo_scale, const Wor
   a.nty = p.my / TY;
   const int nfc = (p.nf + 64 * FPL - 1) / (64 * FPL);
   const int64_t nblk = (int64_t)a.ntx * a.nty * nfc;
-  if (p.echo_type == SAR_ECHO_C64) return launch_body<GridBody<W, SAR_ECHO_C64>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
-  return launch_body<GridBody<W, SAR_ECHO_F16X2>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
+  if (p.echo_type == SAR_ECHO_C64)
+    return launch_body<GridBody<W, SAR_ECHO_C64, TC>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
+  return launch_body<GridBody<W, SAR_ECHO_F16X2, TC>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
 }
 
 }  // namespace grid_impl
 
+// Tile configuration 1 is compiled for kernels of up to 6 taps.
 #define SAR_INSTANTIATE_GRID(W)                                                                    \
   sar_status launch_gridding_w##W(const Plan& p, const void* d_echo, float echo_scale,              \
                                   const Workspace& ws, float2* grid, LaunchSink& sink) {            \
-    return grid_impl::grid_w<W>(p, d_echo, echo_scale, ws, grid, sink);                            \
+    if constexpr ((W) <= 6) {                                                                      \
+      if (p.grid_tile == 1) return grid_impl::grid_w<W, 1>(p, d_echo, echo_scale, ws, grid, sink);  \
+    }                                                                                              \
+    return grid_impl::grid_w<W, 0>(p, d_echo, echo_scale, ws, grid, sink);                        \
   }
 
 }  // namespace sar

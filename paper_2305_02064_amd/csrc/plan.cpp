@@ -214,6 +214,11 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
     p.inv4rc = 1.0 / (4.0 * std::fabs(p.z_focus - p.z_ref));
   }
 
+  // gridding tile: one frequency per lane when the sweep has at most 64
+  // frequencies (two per lane would leave half the lanes idle); the
+  // autotuner may change it by timing
+  p.grid_tile = (p.nf <= 64 && p.w <= kGridTileMaxWidth[1]) ? 1 : 0;
+
   // ---- tables ----
   std::vector<double> fcc(p.nf), kk(p.nf);
   for (int i = 0; i < p.nf; ++i) {

@@ -11,8 +11,10 @@
 namespace sar {
 
 constexpr int kNumStages = 7;
-constexpr int kTileX = 8;       // gridding tile: cells along x
-constexpr int kTileY = 4;       // gridding tile: cells along y
+// gridding tile configurations: cells along x, along y, frequencies per lane
+constexpr int kNumGridTiles = 2;
+constexpr int kGridTiles[kNumGridTiles][3] = {{8, 4, 2}, {8, 8, 1}};
+constexpr int kGridTileMaxWidth[kNumGridTiles] = {8, 6};  // widest kernel compiled per tile
 constexpr int kMaxWidth = 8;    // largest lateral kernel width
 
 // Geometry of one virtual-sample record in the sorted list consumed by the
@@ -42,6 +44,7 @@ struct Plan {
   // derived
   double xc = 0, yc = 0;     // lateral centre of the image grid
   int mx = 0, my = 0, w = 0; // oversampled lateral grid and KB width
+  int grid_tile = 0;         // gridding tile configuration (kGridTiles)
   double kb_beta = 0;
   int mz = 0, wz = 0;        // Stolt grid and ES width
   double es_beta = 0;

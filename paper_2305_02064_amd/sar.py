@@ -66,6 +66,8 @@ class sar_plan_info(ctypes.Structure):
         ("es_beta_z", ctypes.c_double),
         ("n_pair", ctypes.c_int32), ("n_stages", ctypes.c_int32),
         ("workspace_bytes_max", ctypes.c_size_t),
+        ("grid_tile", ctypes.c_int32), ("grid_tile_x", ctypes.c_int32), ("grid_tile_y", ctypes.c_int32),
+        ("grid_freqs_per_lane", ctypes.c_int32),
     ]
 
 
@@ -91,6 +93,8 @@ def library():
         "sar_spectrum": ([vp, vp, i64, vp, f32, vp, vp, vp], i32),
         "sar_image_from_spectrum": ([vp, vp, vp, vp, vp], i32),
         "sar_plan_set_timing": ([vp, ctypes.c_int], i32),
+        "sar_plan_autotune": ([vp, vp, i64, vp, f32, vp, vp, ctypes.POINTER(i32)], i32),
+        "sar_plan_set_grid_tile": ([vp, i32], i32),
         "sar_plan_stage_times": ([vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i64)], i32),
         "sar_server_create": ([ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)], i32),
         "sar_submit": ([vp, vp, vp, i64, vp, ctypes.c_int, f32, vp, ctypes.POINTER(ctypes.c_uint64)], i32),
@@ -399,6 +403,20 @@ class Plan:
         image = self.new_image() if image is None else image
         sar_image_from_spectrum(self.handle, spec, image, self.ws, stream)
         return image
+
+    def set_grid_tile(self, tile):
+        _check(library().sar_plan_set_grid_tile(self.handle, int(tile)))
+        self.info = sar_plan_get_info(self.handle)
+
+    def autotune(self, pos, echo, echo_scale=1.0, stream=None):
+        """Time the gridding tile configurations on this scan and keep the
+        fastest (sar_plan_autotune); returns the chosen configuration."""
+        t = ctypes.c_int32()
+        _check(library().sar_plan_autotune(self.handle, _dptr(pos, "pos", torch.float64), int(pos.shape[0]),
+                                           _dptr(echo, "echo"), float(echo_scale), _dptr(self.ws, "workspace"),
+                                           _stream(stream), ctypes.byref(t)))
+        self.info = sar_plan_get_info(self.handle)
+        return int(t.value)
 
     def close(self):
         if self.handle is not None:

@@ -112,3 +112,11 @@ def test_batch_null_arguments():
     assert lib.sar_batch_workspace_bytes(None, ctypes.byref(b)) == sar.SAR_ERR_INVALID
     assert lib.sar_batch_reconstruct(None, None, None, None, None, None, None, None) == sar.SAR_ERR_INVALID
     assert lib.sar_batch_destroy(None) == sar.SAR_OK
+
+
+def test_grid_tile_arguments():
+    sar = _sar()
+    lib = sar.library()
+    assert lib.sar_plan_set_grid_tile(None, 0) == sar.SAR_ERR_INVALID
+    t = ctypes.c_int32()
+    assert lib.sar_plan_autotune(None, None, 0, None, 1.0, None, None, ctypes.byref(t)) == sar.SAR_ERR_INVALID
