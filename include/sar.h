@@ -80,7 +80,9 @@ typedef enum { SAR_ECHO_C64 = 0, SAR_ECHO_F16X2 = 1 } sar_echo_type;
  * Constraints (SAR_ERR_INVALID otherwise):
  *   n_tx, n_rx >= 1, n_tx * n_rx <= 4096; n_freq >= 1, freq_hz finite,
  *   strictly increasing, > 0;
- *   nx, ny, nz powers of two with 8 <= nx, ny <= 2048 and 2 <= nz <= 512;
+ *   nx, ny powers of two in [8, 2048]; nz 1 or a power of two in [2, 512]
+ *   (nz = 1: one x-y plane at z0, the paper's 2-D image at a known depth,
+ *   Sec. V-A; steps a4-a5 become one exact sum over frequency per column);
  *   dx, dy, dz > 0; the scene reference depth and the image volume in front
  *   of the projection plane (z_focus > z_ref, z0 > z_ref);
  *   0 <= max_pos and max_pos * n_tx * n_rx < 2^31;

@@ -1,4 +1,5 @@
-// Steps a4 + a5: range-migration filter and Stolt map with the z transform.
+// Steps a4 + a5: range-migration filter and Stolt map with the z transform
+// (and its single-plane form for 2-D images).
 //
 // For every (k_x, k_y) column of the spectrum, each frequency sample f_i
 // becomes a non-uniform sample at k_z = sqrt(4 k_i^2 - k_x^2 - k_y^2)
@@ -174,6 +175,64 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
   }
 }
 
+// A single image plane (nz = 1, the paper's 2-D image at a known depth,
+// Sec. V-A): the Stolt map and the z transform collapse to one exact sum per
+// column, Z(p,q) = sum_i F_i exp(+j k_z,i z0) with the filter of Eq. (15),
+// i.e. total phase k_z (z0 - Z_0) in float64.  16 lanes per column take every
+// 16th frequency and reduce with cross-lane shuffles; the (-1)^(P+Q) factor
+// of the lateral inverse transform is folded in as in the 3-D path.
+struct PlaneArgs {
+  const float2* spec;  // [ny][nx][nf]
+  float2* zc;          // [ny][nx]
+  const double* k;     // [nf]
+  int nx, ny, nf;
+  double dkx, dky;
+  double z_cyc;        // (z0 - Z_0) / (2 pi)
+  int64_t ncol;
+};
+
+struct PlaneBody {
+  using Args = PlaneArgs;
+  static constexpr int kThreads = 256;
+  static __device__ __forceinline__ void run(const PlaneArgs& a, uint32_t blk, uint32_t nblk) {
+    constexpr int G = 16;                  // lanes per column
+    constexpr int COLS = kThreads / G;     // columns per block
+    const int cl = threadIdx.x / G;
+    const int gl = threadIdx.x % G;
+    const int64_t ngroups = (a.ncol + COLS - 1) / COLS;
+    for (int64_t grp = blk; grp < ngroups; grp += nblk) {
+      const int64_t col = grp * COLS + cl;
+      const bool live = col < a.ncol;
+      const int64_t colc = live ? col : 0;
+      const int Q = (int)(colc / a.nx);
+      const int P = (int)(colc - (int64_t)Q * a.nx);
+      const double kx = (double)(P - a.nx / 2) * a.dkx;
+      const double ky = (double)(Q - a.ny / 2) * a.dky;
+      const double kp2 = kx * kx + ky * ky;
+      const float2* __restrict__ sp = a.spec + colc * a.nf;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int i = gl; i < a.nf; i += G) {
+        const double k = a.k[i];
+        const double kz2 = 4.0 * k * k - kp2;
+        if (kz2 <= 0.0) continue;
+        const double kz = sqrt(kz2);
+        const float2 v = cmul(sp[i], cis_cycles(kz * a.z_cyc));
+        acc.x = fmaf(v.x, (float)kz, acc.x);
+        acc.y = fmaf(v.y, (float)kz, acc.y);
+      }
+#pragma unroll
+      for (int m = G / 2; m >= 1; m >>= 1) {
+        acc.x += __shfl_xor(acc.x, m, G);
+        acc.y += __shfl_xor(acc.y, m, G);
+      }
+      if (live && gl == 0) {
+        const float sgn = ((P + Q) & 1) ? -1.f : 1.f;
+        a.zc[colc] = make_float2(sgn * acc.x, sgn * acc.y);
+      }
+    }
+  }
+};
+
 template <int MZ>
 sar_status stolt_mz(const Plan& p, const StoltArgs& a, LaunchSink& sink) {
   // enough blocks to fill every CU several times over; each loops over groups
@@ -189,6 +248,22 @@ sar_status stolt_mz(const Plan& p, const StoltArgs& a, LaunchSink& sink) {
 }  // namespace
 
 sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, LaunchSink& sink) {
+  if (p.nz == 1) {
+    PlaneArgs b;
+    b.spec = spec;
+    b.zc = zcube;
+    b.k = p.d_k;
+    b.nx = p.nx;
+    b.ny = p.ny;
+    b.nf = p.nf;
+    b.dkx = 2.0 * M_PI / (p.nx * p.dx);
+    b.dky = 2.0 * M_PI / (p.ny * p.dy);
+    b.z_cyc = (p.z0 - p.z_ref) / (2.0 * M_PI);
+    b.ncol = (int64_t)p.nx * p.ny;
+    const int64_t ngroups = (b.ncol + 15) / 16;
+    const int64_t nblk = ngroups < 256 * 8 ? ngroups : 256 * 8;
+    return launch_body<PlaneBody>(sink, (uint32_t)nblk, 0, b, "plane launch");
+  }
   StoltArgs a;
   a.spec = spec;
   a.zc = zcube;

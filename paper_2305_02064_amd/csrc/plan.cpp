@@ -131,7 +131,8 @@ sar_status validate_desc(const sar_plan_desc* d) {
   auto okn = [](int v, int lo, int hi) { return v >= lo && v <= hi && is_pow2(v); };
   if (!okn(d->nx, 8, 2048) || !okn(d->ny, 8, 2048))
     return fail(SAR_ERR_INVALID, "nx, ny must be powers of two in [8, 2048]");
-  if (!okn(d->nz, 2, 512)) return fail(SAR_ERR_INVALID, "nz must be a power of two in [2, 512]");
+  if (d->nz != 1 && !okn(d->nz, 2, 512))
+    return fail(SAR_ERR_INVALID, "nz must be 1 (one plane) or a power of two in [2, 512]");
   const double g[] = {d->x0, d->y0, d->z0, d->dx, d->dy, d->dz, d->z_ref, d->z_focus};
   for (double v : g)
     if (!finite(v)) return fail(SAR_ERR_INVALID, "non-finite grid or plane");

@@ -221,3 +221,40 @@ def test_autotune_keeps_a_working_tile(torch_cuda, tiny):
     with pytest.raises(sar.SarError) as ei:
         wide.set_grid_tile(1)
     assert ei.value.status == sar.SAR_ERR_UNSUPPORTED
+
+
+def _plane_grid(g, z):
+    return ImageGrid(nx=g.nx, ny=g.ny, nz=1, x0=g.x0, y0=g.y0, z0=z, dx=g.dx, dy=g.dy, dz=g.dz,
+                     z_ref=g.z_ref, z_focus=g.z_focus)
+
+
+def test_single_plane_image_matches_oracle(torch_cuda, tiny):
+    # the 2-D image at a known depth (nz = 1): one exact sum over frequency per column
+    scan, _, _ = tiny
+    g2 = _plane_grid(scan.grid, 0.3)
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, g2)
+    from paper_2305_02064_amd import sar
+    plan = sar.Plan(scan.tx_xy, scan.rx_xy, scan.freq, g2, scan.n_pos)
+    pos, echo, _ = to_device(scan)
+    img = plan.reconstruct(pos, echo).cpu().numpy()
+    assert img.shape == (g2.nx, g2.ny, 1)
+    err = rel_l2(img, ref)
+    print(f"2-D plane image rel-L2 {err:.3e}; peak gpu {peak_index(img)} ref {peak_index(ref)}")
+    assert err <= IMAGE_TOL
+    assert peak_ok(img, ref)
+
+
+def test_single_plane_equals_plane_of_3d_image(torch_cuda, tiny):
+    scan, _, _ = tiny
+    g = scan.grid
+    w = 8
+    g2 = _plane_grid(g, g.z0 + w * g.dz)
+    from paper_2305_02064_amd import sar
+    p3 = make_plan(scan)
+    p2 = sar.Plan(scan.tx_xy, scan.rx_xy, scan.freq, g2, scan.n_pos)
+    pos, echo, _ = to_device(scan)
+    a = p3.reconstruct(pos, echo)[:, :, w].cpu().numpy()
+    b = p2.reconstruct(pos, echo)[:, :, 0].cpu().numpy()
+    err = rel_l2(b, a)
+    print(f"2-D plane vs plane {w} of the 3-D image: rel-L2 {err:.3e}")
+    assert err <= 1e-4
