@@ -168,6 +168,16 @@ sar_status sar_spectrum(sar_plan plan, const double* d_pos, int64_t n_pos, const
 sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* d_image, void* d_workspace,
                                    sar_stream_t stream);
 
+/* Direct back-projection with exact ranges, the paper's gold standard
+ * (Sec. III, Sec. V; ranges of Eq. (2)):
+ *   o_B(u,v,w) = sum_n sum_i s_n(f_i) exp(+j k_i (R_T,n + R_R,n)(x_u, y_v, z_w)),
+ * unit amplitude weight, on the plan's image grid (layouts and arguments as
+ * sar_reconstruct; no workspace).  Cost n_pos * n_pair * n_freq * nx*ny*nz:
+ * meant for small scans, to compare the fast method's images and times.
+ * Asynchronous on `stream`. */
+sar_status sar_backproject(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
+                           void* d_image, sar_stream_t stream);
+
 /* Autotuner: times every compiled gridding tile configuration (8 x 4 cells
  * with 2 frequencies per lane; 8 x 8 cells with 1 frequency per lane, built
  * for kernels of up to 6 taps) on the given scan, which should be

@@ -363,6 +363,16 @@ sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* 
   return run_back(p, (const float2*)d_spectrum, d_image, ws, sink, nullptr, 4);
 }
 
+sar_status sar_backproject(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
+                           void* d_image, sar_stream_t stream) {
+  sar_status st = check_reconstruct_args(plan, n_pos, d_pos, d_echo, d_image);
+  if (st != SAR_OK) return st;
+  Plan& p = plan->p;
+  DeviceGuard g(p.device);
+  DirectSink sink((hipStream_t)stream);
+  return launch_backprojection(p, d_pos, n_pos, d_echo, echo_scale, (float2*)d_image, sink);
+}
+
 sar_status sar_plan_set_timing(sar_plan plan, int enable) {
   if (!plan) return fail(SAR_ERR_INVALID, "plan is NULL");
   DeviceGuard g(plan->p.device);

@@ -17,6 +17,12 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // a += b * s (s real)
+// a += b * c (complex)
+__device__ __forceinline__ void cfma_c(float2& a, float2 b, float2 c) {
+  a.x = fmaf(b.x, c.x, fmaf(-b.y, c.y, a.x));
+  a.y = fmaf(b.x, c.y, fmaf(b.y, c.x, a.y));
+}
+
 __device__ __forceinline__ void cfma(float2& a, float2 b, float s) {
   a.x = fmaf(b.x, s, a.x);
   a.y = fmaf(b.y, s, a.y);

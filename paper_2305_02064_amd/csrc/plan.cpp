@@ -273,6 +273,19 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
   if ((st = upload(&p.d_fcc, fcc)) != SAR_OK) return st;
   if ((st = upload(&p.d_k, kk)) != SAR_OK) return st;
   if ((st = upload(&p.d_pair, pair)) != SAR_OK) return st;
+  {
+    // Tx and Rx offsets per pair for back-projection with exact ranges
+    std::vector<double> txrx(4 * (size_t)p.n_pair);
+    for (int t = 0; t < p.n_tx; ++t)
+      for (int r = 0; r < p.n_rx; ++r) {
+        const int l = t * p.n_rx + r;
+        txrx[4 * l + 0] = p.tx_xy[2 * t];
+        txrx[4 * l + 1] = p.tx_xy[2 * t + 1];
+        txrx[4 * l + 2] = p.rx_xy[2 * r];
+        txrx[4 * l + 3] = p.rx_xy[2 * r + 1];
+      }
+    if ((st = upload(&p.d_txrx, txrx)) != SAR_OK) return st;
+  }
   if ((st = upload(&p.d_deapx, deapx)) != SAR_OK) return st;
   if ((st = upload(&p.d_deapy, deapy)) != SAR_OK) return st;
   if ((st = upload(&p.d_deapz, deapz)) != SAR_OK) return st;
@@ -287,7 +300,7 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
 }
 
 void free_plan(Plan& p) {
-  void* ptrs[] = {p.d_fcc, p.d_k, p.d_pair, p.d_deapx, p.d_deapy, p.d_deapz, p.d_signx,
+  void* ptrs[] = {p.d_fcc, p.d_k, p.d_pair, p.d_txrx, p.d_deapx, p.d_deapy, p.d_deapz, p.d_signx,
                   p.d_signy, p.d_tw_mx, p.d_tw_my, p.d_tw_nx, p.d_tw_ny, p.d_tw_mz};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);

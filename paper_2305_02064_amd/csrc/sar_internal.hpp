@@ -53,6 +53,7 @@ struct Plan {
   double* d_fcc = nullptr;     // f_i / c (cycles per metre) [nf]
   double* d_k = nullptr;       // k_i = 2 pi f_i / c [nf]
   double* d_pair = nullptr;    // [n_pair][4]: midpoint offset (x, y), separation (x, y)
+  double* d_txrx = nullptr;    // [n_pair][4]: Tx offset (x, y), Rx offset (x, y)
   float* d_deapx = nullptr;    // 1 / phi_hat_x(p), p = -nx/2 .. [nx]
   float* d_deapy = nullptr;    // [ny]
   float* d_deapz = nullptr;    // 1 / phi_hat_z(m), m = -nz/2 .. [nz]
@@ -115,6 +116,8 @@ struct FftLines {
 };
 sar_status launch_fft_lines(const FftLines& a, LaunchSink& sink);
 sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, LaunchSink& sink);
+sar_status launch_backprojection(const Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo,
+                                 float echo_scale, float2* image, LaunchSink& sink);
 
 // whole per-scan pipeline on `stream` without stage timing (used by the server)
 sar_status reconstruct_on(const Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,

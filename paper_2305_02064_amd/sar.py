@@ -95,6 +95,7 @@ def library():
         "sar_plan_set_timing": ([vp, ctypes.c_int], i32),
         "sar_plan_autotune": ([vp, vp, i64, vp, f32, vp, vp, ctypes.POINTER(i32)], i32),
         "sar_plan_set_grid_tile": ([vp, i32], i32),
+        "sar_backproject": ([vp, vp, i64, vp, f32, vp, vp], i32),
         "sar_plan_stage_times": ([vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i64)], i32),
         "sar_server_create": ([ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)], i32),
         "sar_submit": ([vp, vp, vp, i64, vp, ctypes.c_int, f32, vp, ctypes.POINTER(ctypes.c_uint64)], i32),
@@ -402,6 +403,14 @@ class Plan:
     def image_from_spectrum(self, spec, image=None, stream=None):
         image = self.new_image() if image is None else image
         sar_image_from_spectrum(self.handle, spec, image, self.ws, stream)
+        return image
+
+    def backproject(self, pos, echo, image=None, echo_scale=1.0, stream=None):
+        """Direct back-projection on the plan's grid (sar_backproject)."""
+        image = self.new_image() if image is None else image
+        _check(library().sar_backproject(self.handle, _dptr(pos, "pos", torch.float64), int(pos.shape[0]),
+                                         _dptr(echo, "echo"), float(echo_scale),
+                                         _dptr(image, "image", torch.complex64), _stream(stream)))
         return image
 
     def set_grid_tile(self, tile):
