@@ -318,7 +318,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
-    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the tiny-scan comparison and the serving runs")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rates", type=str, default="50,200,500")
     args = ap.parse_args()
@@ -409,8 +409,8 @@ def main():
         },
         "input_generation_s": t_gen,
     }
-    out["comparison_tiny"] = comparison_tiny()
     if not args.no_serving:
+        out["comparison_tiny"] = comparison_tiny()
         out["serving"] = serving_bench(scan, pos, plan, args.serve_requests,
                                        [float(r) for r in args.serve_rates.split(",") if r])
     if not args.no_cpu_baseline:
