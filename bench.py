@@ -262,6 +262,25 @@ def serving_bench(big_scan, big_pos, big_plan, n_requests, rates, seed=0):
         t_s = time.perf_counter() - t0
         out["poisson"].append({"rate_per_s": rate, "plain": {"scans_per_s": n_requests / t_p, **pct(lat_p)},
                                "served": {"scans_per_s": n_requests / t_s, **pct(lat_s)}})
+    # echoes starting in pinned host memory (uploads counted): the 16 smallest
+    # uneven scans, 64 requests, all submitted at once
+    small = sorted(range(64), key=lambda i: distinct[i][2].numel())[:16]
+    host = {i: (distinct[i][1].cpu().pin_memory(), distinct[i][2].cpu().pin_memory()) for i in small}
+    hseq = [small[j % 16] for j in range(64)]
+    up_bytes = sum(host[i][0].numel() * 8 + host[i][1].numel() * 8 for i in hseq)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat_h = [srv.wait(t)[0] for t in [srv.submit(distinct[i][0], host[i][0], host[i][1], images[i]) for i in hseq]]
+    t_h = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    lat_d = [srv.wait(t)[0] for t in [srv.submit(distinct[i][0], distinct[i][1], distinct[i][2], images[i])
+                                     for i in hseq]]
+    t_d = time.perf_counter() - t0
+    out["host_input"] = {
+        "workload": "64 requests over the 16 smallest uneven scans, echo and positions in pinned host memory",
+        "scans_per_s": 64 / t_h, "upload_GB_per_s": up_bytes / t_h / 1e9, **pct(lat_h),
+        "pre_resident": {"scans_per_s": 64 / t_d, **pct(lat_d)},
+    }
     srv.close()
     for plan, _, _, _ in distinct[:64]:
         plan.close()
@@ -293,6 +312,16 @@ def comparison_tiny(reps=20):
         torch.cuda.synchronize()
         out[name + "_ms"] = (time.perf_counter() - t0) * 1e3 / reps
     out["workload"] = "tiny scan: 32x16 shots x 8 pairs x 32 freq -> 32x32x16 voxels"
+    # the FP64 oracle on the same scan (host cores), median of 3
+    import oracle
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, scan.grid)
+        ts.append(time.perf_counter() - t0)
+    out["oracle_cpu_ms"] = float(np.median(ts)) * 1e3
+    out["oracle_cpu_threads"] = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get(
+        "OMP_NUM_THREADS", len(os.sched_getaffinity(0)))))
     plan.close()
     raw.close()
     return out
