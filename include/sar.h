@@ -178,19 +178,21 @@ sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* 
 sar_status sar_backproject(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
                            void* d_image, sar_stream_t stream);
 
-/* Autotuner: times every compiled gridding tile configuration (8 x 4 cells
- * with 2 frequencies per lane; 8 x 8 cells with 1 frequency per lane, built
- * for kernels of up to 6 taps) on the given scan, which should be
- * representative of the plan's workload, and keeps the fastest for every
- * later call of this plan.  Runs a0-a2 a few times on `stream` and waits for
- * them (synchronous).  The default before tuning: 1 frequency per lane when
- * the sweep has at most 64 frequencies, else 2.  Tune before creating
+/* Autotuner: times every gridding tile configuration compiled for the plan's
+ * kernel width on the given scan, which should be representative of the
+ * plan's workload, and keeps the fastest for every later call of this plan:
+ *   0: 4 x 4 cells, 2 frequencies per lane (kernels of 3 to 8 taps);
+ *   1: 8 x 8 cells, 1 frequency per lane (3 to 5 taps);
+ *   2: 8 x 4 cells, 2 frequencies per lane (5 and 6 taps).
+ * Runs a0-a2 a few times on `stream` and waits for them (synchronous).  The
+ * default before tuning: tile 1 when the sweep has at most 64 frequencies
+ * (and the width allows it), else tile 0.  Tune before creating
  * batches from the plan and not while other calls use it.  tile_out (may be
  * NULL) receives the chosen configuration.  Arguments as sar_reconstruct. */
 sar_status sar_plan_autotune(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,
                              float echo_scale, void* d_workspace, sar_stream_t stream, int32_t* tile_out);
 
-/* Select a gridding tile configuration directly (0 or 1, as listed for
+/* Select a gridding tile configuration directly (0, 1 or 2, as listed for
  * sar_plan_autotune).  SAR_ERR_UNSUPPORTED if it is not compiled for the
  * plan's kernel width; same restrictions as sar_plan_autotune. */
 sar_status sar_plan_set_grid_tile(sar_plan plan, int32_t tile);

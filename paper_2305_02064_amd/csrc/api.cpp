@@ -269,9 +269,10 @@ sar_status sar_plan_get_info(sar_plan plan, sar_plan_info* info) {
 sar_status sar_plan_set_grid_tile(sar_plan plan, int32_t tile) {
   if (!plan) return fail(SAR_ERR_INVALID, "plan is NULL");
   if (tile < 0 || tile >= kNumGridTiles) return fail(SAR_ERR_INVALID, "no such gridding tile configuration");
-  if (plan->p.w > kGridTileMaxWidth[tile])
-    return fail(SAR_ERR_UNSUPPORTED, "gridding tile " + std::to_string(tile) + " is compiled for kernels of up to " +
-                                         std::to_string(kGridTileMaxWidth[tile]) + " taps");
+  if (!grid_tile_compiled(tile, plan->p.w))
+    return fail(SAR_ERR_UNSUPPORTED, "gridding tile " + std::to_string(tile) + " is compiled for kernels of " +
+                                         std::to_string(kGridTileWidths[tile][0]) + " to " +
+                                         std::to_string(kGridTileWidths[tile][1]) + " taps");
   plan->p.grid_tile = tile;
   return SAR_OK;
 }
@@ -297,7 +298,7 @@ sar_status sar_plan_autotune(sar_plan plan, const double* d_pos, int64_t n_pos, 
   int best = old_tile;
   float best_ms = 0.f;
   for (int t = 0; t < kNumGridTiles && st == SAR_OK; ++t) {
-    if (p.w > kGridTileMaxWidth[t]) continue;
+    if (!grid_tile_compiled(t, p.w)) continue;
     p.grid_tile = t;
     float t_min = 0.f;
     for (int rep = 0; rep < 4 && st == SAR_OK; ++rep) {  // first run warms up

@@ -47,26 +47,40 @@
 namespace sar {
 namespace grid_impl {
 
-// Tile configurations: TX x TY cells per wave, FPL frequencies per lane
-// (64 * FPL per wave); both keep 2 * TX * TY * FPL = 128 accumulator
-// registers.  0: 8 x 4 cells, 2 frequencies (fewer sample visits per
-// frequency); 1: 8 x 8 cells, 1 frequency (less halo, and no idle lanes when
-// a sweep has at most 64 frequencies).
+// Tile configurations: TX x TY cells per wave, FPL frequencies per lane (64 *
+// FPL per wave), CH samples per pipeline chunk (two chunk buffers per wave),
+// and the waves per SIMD the register allocator is asked for:
+//   0: 4 x 4 cells, 2 frequencies: 64 accumulator registers, chunks of 4, four
+//      waves per SIMD up to 4 taps (the occupancy outweighs the extra halo);
+//   1: 8 x 8 cells, 1 frequency: less halo, no idle lanes for sweeps of at most
+//      64 frequencies (128 accumulators, three waves);
+//   2: 8 x 4 cells, 2 frequencies: less halo than tile 0 for 5- and 6-tap kernels.
+// Widths beyond those of kGridTileWidths would spill registers and are not
+// compiled for tiles 1 and 2.
 template <int TC>
 struct TileCfg;
 template <>
 struct TileCfg<0> {
-  static constexpr int TX = 8, TY = 4, FPL = 2;
+  static constexpr int TX = 4, TY = 4, FPL = 2, CH = 4;
+  static constexpr int waves(int W) { return W <= 4 ? 4 : (W <= 6 ? 3 : 2); }
 };
 template <>
 struct TileCfg<1> {
-  static constexpr int TX = 8, TY = 8, FPL = 1;
+  static constexpr int TX = 8, TY = 8, FPL = 1, CH = 6;
+  static constexpr int waves(int W) { return W <= 4 ? 3 : 2; }
 };
-static_assert(TileCfg<0>::TX == kGridTiles[0][0] && TileCfg<0>::TY == kGridTiles[0][1] &&
-                  TileCfg<0>::FPL == kGridTiles[0][2] && TileCfg<1>::TX == kGridTiles[1][0] &&
-                  TileCfg<1>::TY == kGridTiles[1][1] && TileCfg<1>::FPL == kGridTiles[1][2],
+template <>
+struct TileCfg<2> {
+  static constexpr int TX = 8, TY = 4, FPL = 2, CH = 6;
+  static constexpr int waves(int W) { return W <= 4 ? 3 : 2; }
+};
+template <int TC>
+constexpr bool tile_matches_host() {
+  return TileCfg<TC>::TX == kGridTiles[TC][0] && TileCfg<TC>::TY == kGridTiles[TC][1] &&
+         TileCfg<TC>::FPL == kGridTiles[TC][2];
+}
+static_assert(tile_matches_host<0>() && tile_matches_host<1>() && tile_matches_host<2>(),
               "host table of tile configurations");
-constexpr int kChunk = 6;  // samples per pipeline chunk (two chunk buffers per wave)
 
 struct GridArgs {
   const void* rec;
@@ -101,9 +115,8 @@ template <int W, int ET, int TC>
 struct GridBody {
   using Args = GridArgs;
   static constexpr int kThreads = 64;
-  // three waves per SIMD (<= 168 registers) hide the LDS and memory latency;
-  // wider kernels need more registers for their weights
-  static constexpr int kMinWavesPerEU = W <= 4 ? 3 : 2;
+  // waves per SIMD asked of the register allocator (see TileCfg)
+  static constexpr int kMinWavesPerEU = TileCfg<TC>::waves(W);
   static __device__ __forceinline__ void run(const GridArgs& a, uint32_t blk, uint32_t nblk);
 };
 
@@ -115,7 +128,7 @@ __device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint
   constexpr int NBX = TX + W - 1;     // last-tap column offsets touching a tile
   constexpr int NBY = TY + W - 1;     // last-tap row offsets touching a tile
   constexpr int NSEG = 2 * NBY;       // each row of cells may split at the x wrap
-  constexpr int CH = kChunk;          // samples per pipeline chunk
+  constexpr int CH = TileCfg<TC>::CH;  // samples per pipeline chunk
   constexpr int EBH = 512;            // bytes per sample and 64 frequencies of compensated values
   constexpr int EB = FPL * EBH;       // bytes per sample of one chunk buffer
   constexpr int NW = 2 * W;           // weight words per sample (wx then wy)
@@ -473,12 +486,16 @@ sar_status grid_w(const Plan& p, const void* d_echo, float echo_scale, const Wor
 
 }  // namespace grid_impl
 
-// Tile configuration 1 is compiled for kernels of up to 6 taps.
+// Each tile configuration is compiled for the kernel widths of
+// kGridTileWidths; the plan only selects a compiled one.
 #define SAR_INSTANTIATE_GRID(W)                                                                    \
   sar_status launch_gridding_w##W(const Plan& p, const void* d_echo, float echo_scale,              \
                                   const Workspace& ws, float2* grid, LaunchSink& sink) {            \
-    if constexpr ((W) <= 6) {                                                                      \
+    if constexpr ((W) >= kGridTileWidths[1][0] && (W) <= kGridTileWidths[1][1]) {                  \
       if (p.grid_tile == 1) return grid_impl::grid_w<W, 1>(p, d_echo, echo_scale, ws, grid, sink);  \
+    }                                                                                              \
+    if constexpr ((W) >= kGridTileWidths[2][0] && (W) <= kGridTileWidths[2][1]) {                  \
+      if (p.grid_tile == 2) return grid_impl::grid_w<W, 2>(p, d_echo, echo_scale, ws, grid, sink);  \
     }                                                                                              \
     return grid_impl::grid_w<W, 0>(p, d_echo, echo_scale, ws, grid, sink);                        \
   }

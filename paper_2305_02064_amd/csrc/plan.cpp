@@ -216,9 +216,9 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
   }
 
   // gridding tile: one frequency per lane when the sweep has at most 64
-  // frequencies (two per lane would leave half the lanes idle); the
-  // autotuner may change it by timing
-  p.grid_tile = (p.nf <= 64 && p.w <= kGridTileMaxWidth[1]) ? 1 : 0;
+  // frequencies (two per lane would leave half the lanes idle), else the
+  // 4 x 4 tile; the autotuner may change it by timing
+  p.grid_tile = (p.nf <= 64 && grid_tile_compiled(1, p.w)) ? 1 : 0;
 
   // ---- tables ----
   std::vector<double> fcc(p.nf), kk(p.nf);

@@ -11,10 +11,14 @@
 namespace sar {
 
 constexpr int kNumStages = 7;
-// gridding tile configurations: cells along x, along y, frequencies per lane
-constexpr int kNumGridTiles = 2;
-constexpr int kGridTiles[kNumGridTiles][3] = {{8, 4, 2}, {8, 8, 1}};
-constexpr int kGridTileMaxWidth[kNumGridTiles] = {8, 6};  // widest kernel compiled per tile
+// gridding tile configurations: cells along x, along y, frequencies per lane,
+// and the kernel widths each is compiled for
+constexpr int kNumGridTiles = 3;
+constexpr int kGridTiles[kNumGridTiles][3] = {{4, 4, 2}, {8, 8, 1}, {8, 4, 2}};
+constexpr int kGridTileWidths[kNumGridTiles][2] = {{3, 8}, {3, 5}, {5, 6}};  // none spills registers
+constexpr bool grid_tile_compiled(int tile, int w) {
+  return tile >= 0 && tile < kNumGridTiles && w >= kGridTileWidths[tile][0] && w <= kGridTileWidths[tile][1];
+}
 constexpr int kMaxWidth = 8;    // largest lateral kernel width
 
 // Geometry of one virtual-sample record in the sorted list consumed by the
