@@ -45,12 +45,13 @@ struct StoltArgs {
   int64_t ncol;
 };
 
-// exponential-of-semicircle kernel of width WZ at signed distance d (cells)
+// exponential-of-semicircle kernel of width WZ at signed distance d (cells);
+// the hardware square root (about 1 ulp) is ample for a kernel weight
 template <int WZ>
 __device__ __forceinline__ float es_weight(float d, float beta) {
   const float z = d * (2.f / (float)WZ);
   const float q = 1.f - z * z;
-  return q > 0.f ? __expf(beta * (__builtin_sqrtf(q) - 1.f)) : 0.f;
+  return q > 0.f ? __expf(beta * (__builtin_amdgcn_sqrtf(q) - 1.f)) : 0.f;
 }
 
 template <int MZ, int WZ>
@@ -64,6 +65,7 @@ template <int MZ, int WZ>
 __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint32_t blk, uint32_t nblk) {
   constexpr int L2 = MZ / kG;       // points per lane in the first FFT pass
   constexpr int WWIN = WZ + 2;      // register window of cells per lane
+  constexpr int RB = 8;             // samples per lane whose loads are in flight together
   static_assert(MZ % kG == 0 && MZ <= 1024, "Stolt grid of 64..1024 cells");
   // LDS row of one column: MZ cells, then read back as the [16][L2 + 1]
   // padded transposition of the four-step FFT (one pad entry per row, so the
@@ -78,6 +80,31 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
   float2* g = grid[cl];
   const int per = (a.nf + kG - 1) / kG;  // contiguous frequencies per lane
   const int64_t ngroups = (a.ncol + kCols - 1) / kCols;
+
+  // one batch of the lane's run: wavenumbers and spectrum values, all loads
+  // issued before any is used (a bit of `valid` per sample marks the ones
+  // inside the run, so no loaded value is touched before its use)
+  double kb[RB];
+  float2 sb[RB];
+  uint32_t valid = 0;
+  auto load_batch = [&](int64_t colc, int r0) __attribute__((always_inline)) {
+    const float2* __restrict__ sp = a.spec + colc * a.nf;
+    valid = 0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int i = gl * per + r0 + r;
+      const bool ok = r0 + r < per && i < a.nf;
+      const int ic = ok ? i : 0;
+      kb[r] = a.k[ic];
+      sb[r] = sp[ic];
+      valid |= (uint32_t)ok << r;
+    }
+  };
+  auto column_of = [&](int64_t grp) __attribute__((always_inline)) {
+    const int64_t col = grp * kCols + cl;
+    return col < a.ncol ? col : (int64_t)0;
+  };
+  if ((int64_t)blk < ngroups) load_batch(column_of(blk), 0);
 
   for (int64_t grp = blk; grp < ngroups; grp += nblk) {
     const int64_t col = grp * kCols + cl;
@@ -96,7 +123,6 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
       const double ky = (double)(Q - a.ny / 2) * a.dky;
       const double kp2 = kx * kx + ky * ky;
       const float sgn = ((P + Q) & 1) ? -1.f : 1.f;
-      const float2* __restrict__ sp = a.spec + colc * a.nf;
       float2 win[WWIN];
 #pragma unroll
       for (int s2 = 0; s2 < WWIN; ++s2) win[s2] = make_float2(0.f, 0.f);
@@ -113,32 +139,36 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
           win[s2] = make_float2(0.f, 0.f);
         }
       };
-      for (int r = 0; r < per; ++r) {
-        const int i = gl * per + r;
-        if (i >= a.nf) break;
-        const double k = a.k[i];
-        const double kz2 = 4.0 * k * k - kp2;
-        if (kz2 <= 0.0) continue;
-        const double kz = sqrt(kz2);
-        const float2 sv = sp[i];
-        const float2 ph = cis_cycles(kz * a.zmid_minus_zref_cyc);
-        const float2 v = cscale(cmul(sv, ph), (float)kz * sgn);
-        const double gc = kz * a.dz_cells;  // grid position (cells), not wrapped
-        const int c0 = (int)floor(gc - 0.5 * WZ) + 1;
-        if (!open || c0 < wb || c0 + WZ > wb + WWIN) {
-          if (open) flush();
-          wb = c0;
-          open = true;
-        }
-        const float d0 = (float)((double)wb - gc);
+      for (int r0 = 0; r0 < per; r0 += RB) {
+        if (r0 > 0) load_batch(colc, r0);
 #pragma unroll
-        for (int s2 = 0; s2 < WWIN; ++s2) {
-          const float wgt = es_weight<WZ>(d0 + (float)s2, a.es_beta);
-          cfma(win[s2], v, wgt);
+        for (int r = 0; r < RB; ++r) {
+          if (!((valid >> r) & 1u)) continue;
+          const double k = kb[r];
+          const double kz2 = 4.0 * k * k - kp2;
+          if (kz2 <= 0.0) continue;
+          const double kz = sqrt(kz2);
+          const float2 ph = cis_cycles(kz * a.zmid_minus_zref_cyc);
+          const float2 v = cscale(cmul(sb[r], ph), (float)kz * sgn);
+          const double gc = kz * a.dz_cells;  // grid position (cells), not wrapped
+          const int c0 = (int)floor(gc - 0.5 * WZ) + 1;
+          if (!open || c0 < wb || c0 + WZ > wb + WWIN) {
+            if (open) flush();
+            wb = c0;
+            open = true;
+          }
+          const float d0 = (float)((double)wb - gc);
+#pragma unroll
+          for (int s2 = 0; s2 < WWIN; ++s2) {
+            const float wgt = es_weight<WZ>(d0 + (float)s2, a.es_beta);
+            cfma(win[s2], v, wgt);
+          }
         }
       }
       if (open) flush();
     }
+    // the next group's first batch loads while this group's transform runs
+    if (grp + nblk < ngroups) load_batch(column_of(grp + nblk), 0);
     __syncthreads();
 
     // inverse DFT of the MZ cells: four-step with L1 = 16 lanes x L2 points
