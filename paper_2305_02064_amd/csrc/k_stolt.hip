@@ -27,7 +27,7 @@
 namespace sar {
 namespace {
 
-constexpr int kWaves = 4;   // wavefronts per block
+constexpr int kWaves = 1;   // wavefronts per block
 constexpr int kG = 16;      // lanes per column
 constexpr int kCols = kWaves * 64 / kG;  // columns per block
 
@@ -265,9 +265,11 @@ struct PlaneBody {
 
 template <int MZ>
 sar_status stolt_mz(const Plan& p, const StoltArgs& a, LaunchSink& sink) {
-  // enough blocks to fill every CU several times over; each loops over groups
+  // one-wavefront blocks (the LDS of 4 columns each, so 9 fit a CU), many
+  // more than fit at once: each takes about two column groups, and the
+  // hardware queue balances the uneven work of central and evanescent columns
   const int64_t ngroups = (a.ncol + kCols - 1) / kCols;
-  const int64_t nblk = ngroups < 256 * 8 ? ngroups : 256 * 8;
+  const int64_t nblk = ngroups < 256 * 72 ? ngroups : 256 * 72;
   switch (p.wz) {
     case 6: return launch_body<StoltBody<MZ, 6>>(sink, (uint32_t)nblk, 0, a, "stolt launch");
     case 8: return launch_body<StoltBody<MZ, 8>>(sink, (uint32_t)nblk, 0, a, "stolt launch");
