@@ -13,6 +13,7 @@ Irregular Scanning Geometries"), in plain NumPy float64:
   evaluated by its plain definitions: direct 2-D non-uniform DFT, the k_z
   filter of Eq. (15), the Stolt map + z transform as a direct non-uniform sum
   over frequency, and an exact inverse DFT on the uniform (k_x, k_y) grid;
+  also the same image with a reference depth per depth slab;
 * bpa.py       direct back-projection with exact ranges (the gold standard the
   paper compares against, Sec. III / Sec. V).
 
@@ -44,5 +45,7 @@ from .rma import (  # noqa: F401
     image_from_spectrum,
     image_planes_from_spectrum,
     reconstruct_direct,
+    slab_grids,
+    reconstruct_slabs,
 )
 from .bpa import bpa  # noqa: F401

@@ -30,6 +30,8 @@ Array layouts: spectrum [N_y, N_x, N_f] with centred mode index
 (j = p + N_x//2); image [N_x, N_y, N_z].
 """
 
+import types
+
 import numpy as np
 
 from .geometry import residual_path, virtual_samples, wavenumber
@@ -169,3 +171,31 @@ def reconstruct_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation=True):
     """Full image [N_x, N_y, N_z] of one scan (Fig. 3 pipeline, Eq. (16))."""
     spec = spectrum_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation)
     return image_from_spectrum(spec, freq, grid)
+
+
+def slab_grids(grid, n_slabs):
+    """Depth slabs of an image grid: slab j holds planes [j n, (j + 1) n),
+    n = N_z / n_slabs, with its reference depth z_c,j at the z-centre of those
+    planes.  The residual path of Eqs. (7), (12) then uses R_c,j = |z_c,j - Z_0|
+    for the targets of slab j (the paper attributes its depth aberrations to a
+    single reference depth, Sec. V-A)."""
+    if n_slabs < 1 or grid.nz % n_slabs:
+        raise ValueError("n_slabs must divide N_z")
+    n = grid.nz // n_slabs
+    out = []
+    for j in range(n_slabs):
+        z0 = grid.z0 + j * n * grid.dz
+        out.append(types.SimpleNamespace(nx=grid.nx, ny=grid.ny, nz=n, x0=grid.x0, y0=grid.y0, z0=z0,
+                                         dx=grid.dx, dy=grid.dy, dz=grid.dz, z_ref=grid.z_ref,
+                                         z_focus=z0 + 0.5 * (n - 1) * grid.dz))
+    return out
+
+
+def reconstruct_slabs(pos, tx_xy, rx_xy, freq, echo, grid, n_slabs):
+    """Image [N_x, N_y, N_z] with a reference depth per depth slab: slab j is
+    the direct reconstruction of Eq. (16) on the slab's planes, compensated with
+    the slab's own reference depth (slab_grids)."""
+    img = np.zeros((grid.nx, grid.ny, grid.nz), np.complex128)
+    for j, g in enumerate(slab_grids(grid, n_slabs)):
+        img[:, :, j * g.nz:(j + 1) * g.nz] = reconstruct_direct(pos, tx_xy, rx_xy, freq, echo, g)
+    return img

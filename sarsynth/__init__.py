@@ -19,6 +19,7 @@ from .scans import (  # noqa: F401
     config2_scan,
     config4_scan,
     point_scan,
+    depth_pair_scan,
     synth_echo_numpy,
     synth_echo_torch,
     add_noise_numpy,

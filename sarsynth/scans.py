@@ -365,3 +365,28 @@ def point_scan(nx_pos: int, ny_pos: int, pitch: float, target, n_freq: int, grid
     echo = synth_echo_numpy(pos, tx_xy, rx_xy, freq, tgt, amp)
     return Scan(pos=pos, tx_xy=np.asarray(tx_xy, float), rx_xy=np.asarray(rx_xy, float), freq=freq,
                 grid=grid, echo=echo, targets=tgt, amps=amp, meta={"config": "point"})
+
+
+def depth_pair_scan(n_side: int = 32, n_freq: int = 16, depths=(0.15, 0.45)) -> Scan:
+    """Two unit point scatterers on the array axis at the given depths, seen by
+    a wide-baseline array (Tx at x = -3, +3 cm, Rx at x = -1, +1 cm: Tx/Rx
+    separations of 2 and 4 cm) from a flat n_side x n_side lattice of shots at
+    lambda_c/4.  Image 32 x 32 x 16 voxels, lambda_c/4 laterally around the
+    axis, z in [0.1, 0.5) at 25 mm, reference depth 0.3 m (the volume's
+    centre): a scene whose near target keeps a large multistatic residual
+    under a single reference depth."""
+    lam = C0 / 79e9
+    pitch = lam / 4
+    tx = np.array([[-0.03, 0.0], [0.03, 0.0]])
+    rx = np.array([[-0.01, 0.0], [0.01, 0.0]])
+    a = (np.arange(n_side) - (n_side - 1) / 2) * pitch
+    xx, yy = np.meshgrid(a, a, indexing='ij')
+    pos = np.stack([xx.ravel(), yy.ravel(), np.zeros(xx.size)], axis=1)
+    freq = sweep(n_freq)
+    tgt = np.array([[0.0, 0.0, z] for z in depths])
+    amp = np.ones(len(depths), np.complex128)
+    echo = synth_echo_numpy(pos, tx, rx, freq, tgt, amp)
+    grid = ImageGrid(nx=32, ny=32, nz=16, x0=-16 * pitch, y0=-16 * pitch, z0=0.1, dx=pitch, dy=pitch, dz=0.025,
+                     z_ref=0.0, z_focus=0.3)
+    return Scan(pos=pos, tx_xy=tx, rx_xy=rx, freq=freq, grid=grid, echo=echo, targets=tgt, amps=amp,
+                meta={"config": "depth-pair"})

@@ -8,6 +8,7 @@ on tiny inputs, chosen so that a dropped term, a wrong sign, a wrong index or
 a transposed operand fails at least one of them.
 """
 
+import dataclasses
 import json
 import os
 
@@ -17,7 +18,7 @@ import pytest
 import oracle
 from oracle import geometry as geo
 from oracle import rma
-from sarsynth import ImageGrid, awr1443_layout, point_scan, synth_echo_numpy, sweep
+from sarsynth import ImageGrid, awr1443_layout, depth_pair_scan, point_scan, synth_echo_numpy, sweep
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -451,3 +452,68 @@ def test_filter_flattens_spherical_wave_spectrum():
     slope_s = np.polyfit(lk, np.log(np.abs(spec[..., 0][reg])), 1)[0]
     assert abs(slope_f) < 0.3
     assert abs(slope_s + 1.0) < 0.3
+
+
+# --------------------------------------------------------------------------
+# depth slabs: a reference depth per slab (Sec. V-A's depth aberrations)
+# --------------------------------------------------------------------------
+
+def test_slab_grids_partition_and_reference_depths():
+    g = ImageGrid(nx=8, ny=8, nz=16, x0=0.0, y0=0.0, z0=0.1, dx=1e-3, dy=1e-3, dz=0.025, z_ref=0.0, z_focus=0.3)
+    sl = oracle.slab_grids(g, 4)
+    planes = np.concatenate([s.z0 + s.dz * np.arange(s.nz) for s in sl])
+    np.testing.assert_allclose(planes, g.z0 + g.dz * np.arange(g.nz), rtol=0, atol=1e-15)
+    assert [s.nz for s in sl] == [4, 4, 4, 4]
+    np.testing.assert_allclose([s.z_focus for s in sl], [0.1375, 0.2375, 0.3375, 0.4375], rtol=0, atol=1e-15)
+    with pytest.raises(ValueError):
+        oracle.slab_grids(g, 3)
+
+
+def test_one_slab_is_the_single_depth_image_at_the_volume_centre():
+    sc = depth_pair_scan(n_side=16, n_freq=16)
+    g = sc.grid
+    o1 = oracle.reconstruct_slabs(sc.pos, sc.tx_xy, sc.rx_xy, sc.freq, sc.echo, g, 1)
+    gc = dataclasses.replace(g, z_focus=g.z0 + 0.5 * (g.nz - 1) * g.dz)
+    assert np.array_equal(o1, oracle.reconstruct_direct(sc.pos, sc.tx_xy, sc.rx_xy, sc.freq, sc.echo, gc))
+
+
+def test_slab_reference_depth_removes_multistatic_residual():
+    # exact round trip minus the planar model 2 R_0 + beta for the on-axis
+    # near target (0.15 m) of the wide-baseline array: with R_c = 0.3 m the
+    # multistatic term leaves k |d|^2/4 |1/R - 1/R_c| ~ 2.2 rad on the 4 cm
+    # pairs; with the reference at the target's slab centre (0.1375 m, four
+    # slabs over [0.1, 0.5)) it drops below 0.5 rad
+    sc = depth_pair_scan(n_side=2, n_freq=2)
+    k = float(oracle.wavenumber(np.array([79e9]))[0])
+    pos = np.zeros((1, 3))
+    xT, yT, xR, yR, zl = geo.tx_rx_coordinates(pos, sc.tx_xy, sc.rx_xy)
+    xv, yv, dx, dy, dz = geo.virtual_samples(pos, sc.tx_xy, sc.rx_xy, 0.0)
+    tgt = (0.0, 0.0, 0.15)
+    r_exact = geo.round_trip_exact(xT, yT, xR, yR, zl, tgt)
+    r0 = np.sqrt((xv - tgt[0]) ** 2 + (yv - tgt[1]) ** 2 + tgt[2] ** 2)
+    ph_single = np.abs(k * (r_exact - 2 * r0 - geo.residual_path(dx, dy, dz, 0.0, 0.3)))
+    zc = oracle.slab_grids(sc.grid, 4)[0].z_focus
+    ph_slab = np.abs(k * (r_exact - 2 * r0 - geo.residual_path(dx, dy, dz, 0.0, zc)))
+    assert ph_single.max() > 2.0
+    assert ph_slab.max() < 0.5
+
+
+def test_slab_reference_depths_refocus_a_depth_extended_scene():
+    # the same residuals seen in the image: the coherent sum over the four
+    # pairs of the near target falls to about cos((2.2 - 0.55) / 2) ~ 0.68 of
+    # its focused value under one reference depth, and stays above 0.95 of it
+    # with four slabs; both on-axis targets focus higher with slabs, and the
+    # near one (lateral resolution ~10 voxels) stays on its voxel (the far
+    # one's lateral response is ~30 voxels wide, too flat to locate)
+    sc = depth_pair_scan()
+    g = sc.grid
+    o_one = oracle.reconstruct_direct(sc.pos, sc.tx_xy, sc.rx_xy, sc.freq, sc.echo, g)
+    o_sl = oracle.reconstruct_slabs(sc.pos, sc.tx_xy, sc.rx_xy, sc.freq, sc.echo, g, 4)
+    ratio = []
+    for t in sc.targets:
+        w = int(round((t[2] - g.z0) / g.dz))
+        ratio.append(np.abs(o_one[16, 16, w]) / np.abs(o_sl[16, 16, w]))
+    w = int(round((sc.targets[0][2] - g.z0) / g.dz))
+    assert np.unravel_index(np.argmax(np.abs(o_sl[14:19, 14:19, w - 2:w + 3])), (5, 5, 5)) == (2, 2, 2)
+    assert ratio[0] < 0.8
+    assert ratio[1] < 1.0
