@@ -91,7 +91,23 @@ typedef enum { SAR_ECHO_C64 = 0, SAR_ECHO_F16X2 = 1 } sar_echo_type;
  *   error 5 exp(-pi W sqrt(1 - 1/sigma)) meets it;
  *   upsample 0 (automatic = 2) or in [2, 4] (the lateral grid is the next power
  *   of two at or above upsample * n; SAR_ERR_UNSUPPORTED otherwise);
- *   kernel_width 0 (from tol) or 3..8 taps. */
+ *   kernel_width 0 (from tol) or 3..8 taps;
+ *   n_slabs 0 or 1 (one reference depth z_focus for the whole volume) or a
+ *   power of two that divides nz: depth slabs, see below.
+ *
+ * Depth slabs (n_slabs > 1).  The residual path of the compensation (Eqs. (7),
+ * (12)) uses one reference range R_c = |z_focus - z_ref| in its multistatic
+ * term, so targets far from z_focus keep a residual phase that grows with the
+ * Tx/Rx separation; the paper notes the resulting aberrations in depth
+ * (Sec. V-A).  With n_slabs = S > 1 the volume is cut along z into S
+ * slabs of nz / S planes; slab j is reconstructed with its own reference
+ * depth, the z-centre of its planes, z0 + (j nz/S + (nz/S - 1)/2) dz, and
+ * writes only its planes of the image.  z_focus is then unused (it must still
+ * satisfy z_focus > z_ref).  Each slab repeats steps a0-a3, so a call costs
+ * about S single-depth front ends plus one back end; sar_spectrum and
+ * sar_image_from_spectrum (one spectrum per depth) return
+ * SAR_ERR_UNSUPPORTED, and per-stage timing (sar_plan_set_timing) records
+ * nothing for such plans. */
 typedef struct {
   int32_t n_tx;
   int32_t n_rx;
@@ -110,6 +126,7 @@ typedef struct {
   double upsample;
   int32_t kernel_width;
   uint32_t flags;
+  int32_t n_slabs;   /* depth slabs with their own reference depth (0 or 1: none) */
 } sar_plan_desc;
 
 /* What a plan chose (read-only). */
@@ -126,6 +143,7 @@ typedef struct {
   int32_t grid_tile;     /* gridding tile configuration in use (see sar_plan_autotune) */
   int32_t grid_tile_x, grid_tile_y;  /* its cells per wave along x and y */
   int32_t grid_freqs_per_lane;       /* its frequencies per lane (64 lanes per wave) */
+  int32_t n_slabs;       /* depth slabs (1: one reference depth) */
 } sar_plan_info;
 
 /* Create a plan on HIP device `device`: validates the descriptor, chooses the

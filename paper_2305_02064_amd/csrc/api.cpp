@@ -140,14 +140,14 @@ sar_status run_back(const Plan& p, const float2* spec, void* d_image, const Work
   if (tm) tm->mark(first_mark + 2);
   FftLines gx{};
   gx.in = ws.region_a;  // [v][P][w]
-  gx.out = (float2*)d_image;  // [u][v][w]
+  gx.out = (float2*)d_image + p.out_w0;  // [u][v][w], planes [out_w0, out_w0 + nz) of out_nz
   gx.L = p.nx;
   gx.n_outer = p.ny;
   gx.B = p.nz;
   gx.s_in_o = (int64_t)p.nx * p.nz;
   gx.s_in_l = p.nz;
-  gx.s_out_o = p.nz;
-  gx.s_out_k = (int64_t)p.ny * p.nz;
+  gx.s_out_o = p.out_nz;
+  gx.s_out_k = (int64_t)p.ny * p.out_nz;
   gx.n_out = p.nx;
   gx.centred = 0;
   gx.sign = +1;
@@ -178,6 +178,15 @@ sar_status reconstruct_on(const Plan& p, const double* d_pos, int64_t n_pos, con
 sar_status describe_reconstruct(const Plan& p, const double* d_pos, int64_t n_pos, int64_t n_pos_grid,
                                 const void* d_echo, float echo_scale, void* d_image, void* d_workspace,
                                 LaunchSink& sink) {
+  // depth slabs: each slab runs the whole pipeline with its own reference
+  // depth and writes its planes of the image (a slab's workspace layout fits
+  // inside the full plan's)
+  for (const auto& sub : p.slabs) {
+    sar_status st = describe_reconstruct(*sub, d_pos, n_pos, n_pos_grid, d_echo, echo_scale, d_image, d_workspace,
+                                         sink);
+    if (st != SAR_OK) return st;
+  }
+  if (!p.slabs.empty()) return SAR_OK;
   Workspace ws;
   workspace_bytes(p, n_pos_grid, &ws, (char*)d_workspace);
   sar_status st = run_front(p, d_pos, n_pos, n_pos_grid, d_echo, echo_scale, ws.region_a, ws, sink, nullptr);
@@ -263,6 +272,7 @@ sar_status sar_plan_get_info(sar_plan plan, sar_plan_info* info) {
   info->grid_tile_x = kGridTiles[p.grid_tile][0];
   info->grid_tile_y = kGridTiles[p.grid_tile][1];
   info->grid_freqs_per_lane = kGridTiles[p.grid_tile][2];
+  info->n_slabs = p.slabs.empty() ? 1 : (int32_t)p.slabs.size();
   return SAR_OK;
 }
 
@@ -274,6 +284,7 @@ sar_status sar_plan_set_grid_tile(sar_plan plan, int32_t tile) {
                                          std::to_string(kGridTileWidths[tile][0]) + " to " +
                                          std::to_string(kGridTileWidths[tile][1]) + " taps");
   plan->p.grid_tile = tile;
+  for (auto& sub : plan->p.slabs) sub->grid_tile = tile;
   return SAR_OK;
 }
 
@@ -318,6 +329,7 @@ sar_status sar_plan_autotune(sar_plan plan, const double* d_pos, int64_t n_pos, 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   p.grid_tile = st == SAR_OK ? best : old_tile;
+  for (auto& sub : p.slabs) sub->grid_tile = p.grid_tile;
   if (tile_out) *tile_out = p.grid_tile;
   return st;
 }
@@ -328,10 +340,12 @@ sar_status sar_reconstruct(sar_plan plan, const double* d_pos, int64_t n_pos, co
   if (st != SAR_OK) return st;
   Plan& p = plan->p;
   DeviceGuard g(p.device);
-  Workspace ws;
-  workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
   hipStream_t s = (hipStream_t)stream;
   DirectSink sink(s);
+  if (!p.slabs.empty())  // depth slabs: no per-stage timing
+    return describe_reconstruct(p, d_pos, n_pos, n_pos, d_echo, echo_scale, d_image, d_workspace, sink);
+  Workspace ws;
+  workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
   Timer tm(p, s, p.timing);
   if ((st = run_front(p, d_pos, n_pos, n_pos, d_echo, echo_scale, ws.region_a, ws, sink, &tm)) != SAR_OK) return st;
   if ((st = run_back(p, ws.region_a, d_image, ws, sink, &tm, 4)) != SAR_OK) return st;
@@ -343,6 +357,7 @@ sar_status sar_spectrum(sar_plan plan, const double* d_pos, int64_t n_pos, const
                         void* d_spectrum, void* d_workspace, sar_stream_t stream) {
   sar_status st = check_call(plan, n_pos, d_pos, d_echo, d_spectrum, d_workspace);
   if (st != SAR_OK) return st;
+  if (!plan->p.slabs.empty()) return fail(SAR_ERR_UNSUPPORTED, "a depth-slab plan has one spectrum per slab");
   Plan& p = plan->p;
   DeviceGuard g(p.device);
   Workspace ws;
@@ -356,6 +371,7 @@ sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* 
   sar_status st = check_call(plan, 0, nullptr, nullptr, d_image, d_workspace);
   if (st != SAR_OK) return st;
   if (!d_spectrum) return fail(SAR_ERR_INVALID, "spectrum pointer is NULL");
+  if (!plan->p.slabs.empty()) return fail(SAR_ERR_UNSUPPORTED, "a depth-slab plan has one spectrum per slab");
   Plan& p = plan->p;
   DeviceGuard g(p.device);
   Workspace ws;

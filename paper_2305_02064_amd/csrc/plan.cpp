@@ -150,6 +150,8 @@ sar_status validate_desc(const sar_plan_desc* d) {
   if (!(d->kernel_width == 0 || (d->kernel_width >= 3 && d->kernel_width <= kMaxWidth)))
     return fail(SAR_ERR_INVALID, "kernel_width must be 0 or 3..8");
   if (d->flags & ~SAR_NO_COMPENSATION) return fail(SAR_ERR_INVALID, "unknown flag bits");
+  if (!(d->n_slabs == 0 || d->n_slabs == 1 || (d->n_slabs > 1 && is_pow2(d->n_slabs) && d->n_slabs <= d->nz)))
+    return fail(SAR_ERR_INVALID, "n_slabs must be 0, 1 or a power of two that divides nz");
   return SAR_OK;
 }
 
@@ -169,6 +171,8 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
   p.nx = d->nx;
   p.ny = d->ny;
   p.nz = d->nz;
+  p.out_w0 = 0;
+  p.out_nz = d->nz;
   p.x0 = d->x0;
   p.y0 = d->y0;
   p.z0 = d->z0;
@@ -296,10 +300,32 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
   if ((st = upload(&p.d_tw_nx, twiddles(p.nx, +1))) != SAR_OK) return st;
   if ((st = upload(&p.d_tw_ny, twiddles(p.ny, +1))) != SAR_OK) return st;
   if ((st = upload(&p.d_tw_mz, twiddles(p.mz, +1))) != SAR_OK) return st;
+
+  // depth slabs: slab j covers planes [j n, (j + 1) n), n = nz / S, and takes
+  // the z-centre of its planes as reference depth
+  if (d->n_slabs > 1) {
+    const int n = d->nz / d->n_slabs;
+    for (int j = 0; j < d->n_slabs; ++j) {
+      sar_plan_desc dj = *d;
+      dj.n_slabs = 0;
+      dj.nz = n;
+      dj.z0 = d->z0 + (double)j * n * d->dz;
+      dj.z_focus = dj.z0 + 0.5 * (n - 1) * d->dz;
+      std::unique_ptr<Plan> sub(new (std::nothrow) Plan());
+      if (!sub) return fail(SAR_ERR_NOMEM, "host allocation failed");
+      st = build_plan(&dj, device, *sub);
+      sub->out_w0 = j * n;
+      sub->out_nz = d->nz;
+      p.slabs.push_back(std::move(sub));  // freed with the plan, also after a failure
+      if (st != SAR_OK) return st;
+    }
+  }
   return SAR_OK;
 }
 
 void free_plan(Plan& p) {
+  for (auto& sub : p.slabs) free_plan(*sub);
+  p.slabs.clear();
   void* ptrs[] = {p.d_fcc, p.d_k, p.d_pair, p.d_txrx, p.d_deapx, p.d_deapy, p.d_deapz, p.d_signx,
                   p.d_signy, p.d_tw_mx, p.d_tw_my, p.d_tw_nx, p.d_tw_ny, p.d_tw_mz};
   for (void* q : ptrs)

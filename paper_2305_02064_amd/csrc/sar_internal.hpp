@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "sar.h"
@@ -68,6 +69,12 @@ struct Plan {
   float2* d_tw_nx = nullptr;   // exp(+j 2 pi i / nx) [nx]
   float2* d_tw_ny = nullptr;
   float2* d_tw_mz = nullptr;   // exp(+j 2 pi i / mz) [mz]
+  // output placement: this plan's nz planes are planes [out_w0, out_w0 + nz)
+  // of an image with out_nz planes (a depth slab writes into the full image)
+  int out_w0 = 0, out_nz = 0;
+  // depth slabs: one sub-plan per slab, each with its own reference depth
+  // (empty for a single-depth plan)
+  std::vector<std::unique_ptr<Plan>> slabs;
   // timing
   bool timing = false;
   std::vector<hipEvent_t> events;  // kNumStages + 1 per recorded call

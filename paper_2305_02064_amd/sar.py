@@ -55,6 +55,7 @@ class sar_plan_desc(ctypes.Structure):
         ("echo_type", ctypes.c_int32),
         ("tol", ctypes.c_double), ("upsample", ctypes.c_double),
         ("kernel_width", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("n_slabs", ctypes.c_int32),
     ]
 
 
@@ -68,6 +69,7 @@ class sar_plan_info(ctypes.Structure):
         ("workspace_bytes_max", ctypes.c_size_t),
         ("grid_tile", ctypes.c_int32), ("grid_tile_x", ctypes.c_int32), ("grid_tile_y", ctypes.c_int32),
         ("grid_freqs_per_lane", ctypes.c_int32),
+        ("n_slabs", ctypes.c_int32),
     ]
 
 
@@ -158,7 +160,7 @@ def _stream(stream):
 
 
 def sar_plan_create(tx_xy, rx_xy, freq_hz, nx, ny, nz, x0, y0, z0, dx, dy, dz, z_ref, z_focus, max_pos,
-                    echo_type=SAR_ECHO_C64, tol=0.0, upsample=0.0, kernel_width=0, flags=0, device=0):
+                    echo_type=SAR_ECHO_C64, tol=0.0, upsample=0.0, kernel_width=0, flags=0, n_slabs=0, device=0):
     """Create a plan (see sar_plan_create in include/sar.h); returns an opaque handle."""
     import numpy as np
     lib = library()
@@ -170,7 +172,7 @@ def sar_plan_create(tx_xy, rx_xy, freq_hz, nx, ny, nz, x0, y0, z0, dx, dy, dz, z
         n_tx=len(tx), n_rx=len(rx), tx_xy=tx.ctypes.data_as(dp), rx_xy=rx.ctypes.data_as(dp),
         n_freq=len(fr), freq_hz=fr.ctypes.data_as(dp), z_ref=z_ref, z_focus=z_focus,
         nx=nx, ny=ny, nz=nz, x0=x0, y0=y0, z0=z0, dx=dx, dy=dy, dz=dz, max_pos=max_pos,
-        echo_type=echo_type, tol=tol, upsample=upsample, kernel_width=kernel_width, flags=flags)
+        echo_type=echo_type, tol=tol, upsample=upsample, kernel_width=kernel_width, flags=flags, n_slabs=n_slabs)
     h = ctypes.c_void_p()
     _check(lib.sar_plan_create(ctypes.byref(d), int(device), ctypes.byref(h)))
     return h

@@ -58,6 +58,9 @@ def _desc_kwargs(**over):
     (dict(tol=0.5), "tol"),
     (dict(flags=0x80), "flag"),
     (dict(echo_type=7), "echo type"),
+    (dict(n_slabs=3), "n_slabs"),
+    (dict(n_slabs=32), "n_slabs"),
+    (dict(n_slabs=-2), "n_slabs"),
 ])
 def test_descriptor_validation(bad, needle):
     sar = _sar()
