@@ -239,6 +239,8 @@ def serving_bench(big_scan, big_pos, big_plan, n_requests, rates, seed=0):
             e = torch.cuda.Event()
             e.record(stream)
             pending.append((arr[k], e))
+            if k % 500 == 499:
+                print(f"poisson {rate}/s plain: {k + 1} of {n_requests} submitted", file=sys.stderr, flush=True)
         while pending:
             retire(t0)
         t_p = time.perf_counter() - t0
@@ -257,6 +259,8 @@ def serving_bench(big_scan, big_pos, big_plan, n_requests, rates, seed=0):
                         still.append(t)
                 live = still
             live.append(srv.submit(distinct[i][0], distinct[i][1], distinct[i][2], images[i]))
+            if k % 500 == 499:
+                print(f"poisson {rate}/s served: {k + 1} of {n_requests} submitted", file=sys.stderr, flush=True)
         for t in live:
             lat_s.append(srv.wait(t)[0])
         t_s = time.perf_counter() - t0

@@ -98,17 +98,19 @@ sar_status launch_lb(const FftLines& a, LaunchSink& sink) {
 }  // namespace
 
 sar_status launch_fft_lines(const FftLines& a, LaunchSink& sink) {
-  // batch columns per block chosen so one block's LDS stays near 64 KiB
+  // batch columns per block chosen so one block's LDS stays near 64 KiB; where
+  // L is not a square, L1 > L2 so that every thread of the block loads and
+  // transforms in the first pass (the load-bound one)
   switch (a.L) {
-    case 8: return launch_lb<2, 4, 16>(a, sink);
+    case 8: return launch_lb<4, 2, 16>(a, sink);
     case 16: return launch_lb<4, 4, 16>(a, sink);
-    case 32: return launch_lb<4, 8, 16>(a, sink);
+    case 32: return launch_lb<8, 4, 16>(a, sink);
     case 64: return launch_lb<8, 8, 16>(a, sink);
-    case 128: return launch_lb<8, 16, 16>(a, sink);
+    case 128: return launch_lb<16, 8, 16>(a, sink);
     case 256: return launch_lb<16, 16, 16>(a, sink);
-    case 512: return launch_lb<16, 32, 16>(a, sink);
+    case 512: return launch_lb<32, 16, 16>(a, sink);
     case 1024: return launch_lb<32, 32, 8>(a, sink);
-    case 2048: return launch_lb<32, 64, 4>(a, sink);
+    case 2048: return launch_lb<64, 32, 4>(a, sink);
     case 4096: return launch_lb<64, 64, 2>(a, sink);
     default: return fail(SAR_ERR_UNSUPPORTED, "FFT length not supported: " + std::to_string(a.L));
   }
