@@ -101,6 +101,82 @@ def cpu_baseline(scan, echo_host_fn):
     }
 
 
+def oracle_uneven(n_small=8, n_random=4, full_macs=1.2e11, seed=0):
+    """The FP64 oracle beside the GPU on scans of the uneven batch: the n_small
+    cheapest of the 64 (by direct-NUDFT size N_v x S^2 x N_f) and n_random others
+    drawn with a fixed seed.  A scan whose NUDFT exceeds full_macs complex
+    multiply-adds is timed on a sample (the NUDFT for enough frequencies to
+    reach about full_macs, the Stolt sum for 4 k_y rows, the inverse DFT in full)
+    and extrapolated; the others run the whole oracle.  Echoes are seeded random
+    values (the oracle's work does not depend on them)."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2305_02064_amd import sar
+    from sarsynth import config4_scan
+    scans = [config4_scan(sd, with_echo=False) for sd in range(64)]
+    cost = [sc.n_pos * sc.n_pair * sc.grid.nx * sc.grid.ny * sc.n_freq for sc in scans]
+    order = sorted(range(64), key=lambda i: cost[i])
+    rng = np.random.default_rng(seed)
+    pick = order[:n_small] + sorted(rng.choice(order[n_small:], n_random, replace=False).tolist())
+    rows_out = []
+    dev = torch.device("cuda", 0)
+    for i in pick:
+        sc = scans[i]
+        g = sc.grid
+        er = np.random.default_rng(100 + i)
+        echo = (er.standard_normal((sc.n_pos, sc.n_pair, sc.n_freq))
+                + 1j * er.standard_normal((sc.n_pos, sc.n_pair, sc.n_freq)))
+        plan = sar.Plan(sc.tx_xy, sc.rx_xy, sc.freq, g, sc.n_pos)
+        pos_d = torch.from_numpy(np.ascontiguousarray(sc.pos)).to(dev)
+        echo_d = torch.from_numpy(echo.astype(np.complex64)).to(dev)
+        img = plan.new_image()
+        plan.reconstruct(pos_d, echo_d, img)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            plan.reconstruct(pos_d, echo_d, img)
+        torch.cuda.synchronize()
+        gpu_ms = (time.perf_counter() - t0) / 5 * 1e3
+        plan.close()
+        if cost[i] <= full_macs:
+            t0 = time.perf_counter()
+            oracle.reconstruct_direct(sc.pos, sc.tx_xy, sc.rx_xy, sc.freq, echo, g)
+            cpu_s = time.perf_counter() - t0
+            how = "full"
+        else:
+            kf = max(1, int(full_macs // (sc.n_pos * sc.n_pair * g.nx * g.ny)))
+            k = oracle.wavenumber(sc.freq)
+            t0 = time.perf_counter()
+            xv, yv, dxx, dyy, dzz = oracle.virtual_samples(sc.pos, sc.tx_xy, sc.rx_xy, g.z_ref)
+            beta = oracle.residual_path(dxx, dyy, dzz, g.z_ref, g.z_focus).ravel()
+            shat = oracle.compensate(echo[:, :, :kf].reshape(-1, kf), k[:kf], beta)
+            kx, ky, xc, yc = oracle.mode_axes(g.nx, g.ny, g.x0, g.y0, g.dx, g.dy)
+            oracle.nudft2(shat, xv.ravel(), yv.ravel(), kx, ky, xc, yc, block=32768)
+            t_nu = time.perf_counter() - t0
+            rows = 4
+            spec_rows = er.standard_normal((rows, g.nx, sc.n_freq)) + 1j * er.standard_normal((rows, g.nx, sc.n_freq))
+            t0 = time.perf_counter()
+            kz, mask = oracle.axial_wavenumber(k, kx, ky[:rows])
+            zc = oracle.stolt_direct(oracle.rma_filter(spec_rows, kz, mask, g.z_ref), kz, mask,
+                                     g.z0 + g.dz * np.arange(g.nz))
+            t_st = time.perf_counter() - t0
+            zfull = np.zeros((g.ny, g.nx, g.nz), np.complex128)
+            zfull[:rows] = zc
+            t0 = time.perf_counter()
+            oracle.idft2(zfull)
+            t_id = time.perf_counter() - t0
+            cpu_s = t_nu * sc.n_freq / kf + t_st * g.ny / rows + t_id
+            how = f"extrapolated ({kf} of {sc.n_freq} frequencies, {rows} of {g.ny} rows)"
+        rows_out.append({"seed": i, "side": int(round(np.sqrt(sc.n_pos))), "n_freq": sc.n_freq,
+                         "image": [g.nx, g.ny, g.nz], "gpu_ms": gpu_ms, "oracle_s": cpu_s, "oracle": how,
+                         "speedup": cpu_s * 1e3 / gpu_ms})
+        print(f"oracle on uneven scan {i}: {cpu_s:.2f} s ({how}), GPU {gpu_ms:.3f} ms", file=sys.stderr, flush=True)
+    threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))))
+    return {"scans": rows_out, "cores": threads,
+            "selection": f"{n_small} cheapest of the 64 uneven-batch scans plus {n_random} others (seed {seed})"}
+
+
 def serving_bench(big_scan, big_pos, big_plan, n_requests, rates, seed=0):
     """Served vs plain per-scan path on a stream of scans shaped like the
     serving workload: 95% scans of the uneven batch (64 distinct scans, side
@@ -354,6 +430,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the tiny-scan comparison and the serving runs")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rates", type=str, default="50,200,500")
+    ap.add_argument("--oracle-uneven", action="store_true",
+                    help="also time the FP64 oracle beside the GPU on 12 scans of the uneven batch (minutes of CPU)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the library forms each image on a single device (got --gpus {args.gpus})",
@@ -450,6 +528,8 @@ def main():
         def echo_host(kk):
             return echo[:, :, :kk].cpu().numpy().astype(np.complex128)
         out["cpu_baseline"] = cpu_baseline(scan, echo_host)
+    if args.oracle_uneven:
+        out["oracle_uneven"] = oracle_uneven()
     print(json.dumps(out))
     plan.close()
 
