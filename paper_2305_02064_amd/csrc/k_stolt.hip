@@ -45,13 +45,25 @@ struct StoltArgs {
   int64_t ncol;
 };
 
-// exponential-of-semicircle kernel of width WZ at signed distance d (cells);
-// the hardware square root (about 1 ulp) is ample for a kernel weight
-template <int WZ>
-__device__ __forceinline__ float es_weight(float d, float beta) {
-  const float z = d * (2.f / (float)WZ);
-  const float q = 1.f - z * z;
-  return q > 0.f ? __expf(beta * (__builtin_amdgcn_sqrtf(q) - 1.f)) : 0.f;
+// exponential-of-semicircle kernel exp(beta (sqrt(1 - z^2) - 1)) at z = 2 d / WZ
+// (d the signed distance in cells), written exp2(b2 sqrt(1 - z^2) - b2) with
+// b2 = beta log2(e); the hardware square root and exp2 (about 1 ulp each) are
+// ample for a kernel weight
+__device__ __forceinline__ float es_weight(float z, float b2) {
+  const float q = fmaf(-z, z, 1.f);
+  return q > 0.f ? __builtin_amdgcn_exp2f(fmaf(b2, __builtin_amdgcn_sqrtf(q), -b2)) : 0.f;
+}
+
+// square root of a positive, normal float64: hardware reciprocal square root
+// refined by two Newton steps (relative error far below 1e-12, ample for the
+// k_z of a phase argument)
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * r;
+  double s = x * r;
+  s = fma(h, fma(-s, s, x), s);
+  s = fma(h, fma(-s, s, x), s);
+  return s;
 }
 
 template <int MZ, int WZ>
@@ -80,6 +92,7 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
   float2* g = grid[cl];
   const int per = (a.nf + kG - 1) / kG;  // contiguous frequencies per lane
   const int64_t ngroups = (a.ncol + kCols - 1) / kCols;
+  const float b2 = a.es_beta * 1.4426950408889634f;  // beta log2(e)
 
   // one batch of the lane's run: wavenumbers and spectrum values, all loads
   // issued before any is used (a bit of `valid` per sample marks the ones
@@ -147,7 +160,7 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
           const double k = kb[r];
           const double kz2 = 4.0 * k * k - kp2;
           if (kz2 <= 0.0) continue;
-          const double kz = sqrt(kz2);
+          const double kz = sqrt_pos(kz2);
           const float2 ph = cis_cycles(kz * a.zmid_minus_zref_cyc);
           const float2 v = cscale(cmul(sb[r], ph), (float)kz * sgn);
           const double gc = kz * a.dz_cells;  // grid position (cells), not wrapped
@@ -157,10 +170,10 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
             wb = c0;
             open = true;
           }
-          const float d0 = (float)((double)wb - gc);
+          const float z0 = (float)((double)wb - gc) * (2.f / (float)WZ);
 #pragma unroll
           for (int s2 = 0; s2 < WWIN; ++s2) {
-            const float wgt = es_weight<WZ>(d0 + (float)s2, a.es_beta);
+            const float wgt = es_weight(fmaf((float)s2, 2.f / (float)WZ, z0), b2);
             cfma(win[s2], v, wgt);
           }
         }
