@@ -75,6 +75,12 @@ typedef enum { SAR_ECHO_C64 = 0, SAR_ECHO_F16X2 = 1 } sar_echo_type;
 
 /* flags */
 #define SAR_NO_COMPENSATION 0x1u /* beta = 0: plain RMA on raw multi-planar data (Sec. III ablation) */
+/* Precision diagnostic: the phase arguments (k beta of the compensation, the
+ * Stolt pre-phase k_z (z - Z_0) and grid position) and the position-to-grid
+ * offsets in float32 instead of float64.  Not for production: it exists to
+ * measure what the float64 arguments buy.  Needs complex64 echo and a 4-tap
+ * lateral kernel (SAR_ERR_UNSUPPORTED otherwise). */
+#define SAR_FP32_ARGS 0x2u
 
 /* Plan descriptor: array geometry, frequency sweep and image grid.
  * Constraints (SAR_ERR_INVALID otherwise):

@@ -35,6 +35,11 @@ __device__ __forceinline__ float2 cis_cycles(double t) {
   const float r = (float)fr;
   return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
 }
+// the same with the argument formed and reduced in float32 (precision diagnostic)
+__device__ __forceinline__ float2 cis_cycles_f32(float t) {
+  const float r = __builtin_amdgcn_fractf(t);
+  return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+}
 
 // ---------------------------------------------------------------------------
 // compile-time loops and twiddles

@@ -26,6 +26,7 @@ struct GeoArgs {
   double z_ref;
   double beta_sign;      // 2 sign(Z_0 - z_c), or 0 without compensation
   double kb_beta, inv_i0_beta;
+  int fp32;              // precision diagnostic: offsets and beta in float32
 };
 
 // Modified Bessel function of the first kind, order 0, by its power series
@@ -65,6 +66,32 @@ __device__ __forceinline__ void grid_coord(double rel, double scale, int m, int 
   c0 = (int)floor(t - 0.5 * W) + 1;
 }
 
+// the same in float32 (precision diagnostic)
+__device__ __forceinline__ void grid_coord_f32(float rel, float scale, int m, int W, double& g, int& c0) {
+  float t = rel * scale;
+  t -= floorf(t / (float)m) * (float)m;
+  if (t >= (float)m) t -= (float)m;
+  g = t;
+  c0 = (int)floorf(t - 0.5f * (float)W) + 1;
+}
+
+// grid coordinates of virtual sample (shot m, pair l); keys and records call
+// this one function, so both place a sample in the same cell
+__device__ __forceinline__ void sample_cells(const GeoArgs& g, int64_t m, int l, int W, double& gx, int& cx,
+                                             double& gy, int& cy) {
+  if (g.fp32) {
+    const float xv = (float)g.pos[3 * m + 0] + (float)g.pair[4 * l + 0];
+    const float yv = (float)g.pos[3 * m + 1] + (float)g.pair[4 * l + 1];
+    grid_coord_f32(xv - (float)g.xc, (float)g.gsx, g.mx, W, gx, cx);
+    grid_coord_f32(yv - (float)g.yc, (float)g.gsy, g.my, W, gy, cy);
+  } else {
+    const double xv = g.pos[3 * m + 0] + g.pair[4 * l + 0];
+    const double yv = g.pos[3 * m + 1] + g.pair[4 * l + 1];
+    grid_coord(xv - g.xc, g.gsx, g.mx, W, gx, cx);
+    grid_coord(yv - g.yc, g.gsy, g.my, W, gy, cy);
+  }
+}
+
 __device__ __forceinline__ int wrap(int c, int m) { return c < 0 ? c + m : (c >= m ? c - m : c); }
 
 struct ZeroBody {
@@ -94,12 +121,9 @@ struct KeysBody {
     if (n >= a.g.n_v) return;
     const int64_t m = n / a.g.n_pair;
     const int l = (int)(n - m * a.g.n_pair);
-    const double xv = a.g.pos[3 * m + 0] + a.g.pair[4 * l + 0];
-    const double yv = a.g.pos[3 * m + 1] + a.g.pair[4 * l + 1];
     double gx, gy;
     int cx, cy;
-    grid_coord(xv - a.g.xc, a.g.gsx, a.g.mx, W, gx, cx);
-    grid_coord(yv - a.g.yc, a.g.gsy, a.g.my, W, gy, cy);
+    sample_cells(a.g, m, l, W, gx, cx, gy, cy);
     const int k = wrap(cy, a.g.my) * a.g.mx + wrap(cx, a.g.mx);
     a.key[n] = k;
     a.rank[n] = atomicAdd(&a.count[k], 1);
@@ -263,7 +287,8 @@ struct SortCellsBody {
 };
 
 // One thread per sorted slot: the record of the slot's sample, its geometry
-// recomputed in float64 from the shot position.
+// recomputed in float64 (float32 for the precision diagnostic) from the shot
+// position.
 template <int W>
 struct RecordsBody {
   struct Args {
@@ -278,18 +303,17 @@ struct RecordsBody {
     const int64_t n = a.order[s];
     const int64_t m = n / a.g.n_pair;
     const int l = (int)(n - m * a.g.n_pair);
-    const double xv = a.g.pos[3 * m + 0] + a.g.pair[4 * l + 0];
-    const double yv = a.g.pos[3 * m + 1] + a.g.pair[4 * l + 1];
-    const double dzv = a.g.pos[3 * m + 2] - a.g.z_ref;
     double gx, gy;
     int cx, cy;
-    grid_coord(xv - a.g.xc, a.g.gsx, a.g.mx, W, gx, cx);
-    grid_coord(yv - a.g.yc, a.g.gsy, a.g.my, W, gy, cy);
+    sample_cells(a.g, m, l, W, gx, cx, gy, cy);
     SampleRec<W> r;
     r.src = (int32_t)n;
     r.cx = (int16_t)wrap(wrap(cx, a.g.mx) + W - 1, a.g.mx);
     r.cy = (int16_t)wrap(wrap(cy, a.g.my) + W - 1, a.g.my);
-    r.beta = a.g.beta_sign * dzv + a.g.pair[4 * l + 2];
+    if (a.g.fp32)
+      r.beta = (float)a.g.beta_sign * ((float)a.g.pos[3 * m + 2] - (float)a.g.z_ref) + (float)a.g.pair[4 * l + 2];
+    else
+      r.beta = a.g.beta_sign * (a.g.pos[3 * m + 2] - a.g.z_ref) + a.g.pair[4 * l + 2];
     const double fx = (double)cx - gx;
     const double fy = (double)cy - gy;
 #pragma unroll
@@ -323,6 +347,7 @@ sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, in
   g.z_ref = p.z_ref;
   g.beta_sign = p.beta_sign;
   g.kb_beta = p.kb_beta;
+  g.fp32 = (p.flags & SAR_FP32_ARGS) ? 1 : 0;
   // 1 / I0(beta) evaluated with the same series on the host
   {
     const double q = 0.25 * p.kb_beta * p.kb_beta;

@@ -111,6 +111,10 @@ __device__ __forceinline__ void dma_quad(const void* src, void* lds_base) {
   __builtin_amdgcn_global_load_lds(src, (void __attribute__((address_space(3)))*)lds_base, 16, 0, 0);
 }
 
+// echo-type template value of the precision diagnostic: complex64 echo with the
+// compensation argument k * beta formed and reduced in float32
+constexpr int kEchoC64Fp32Args = 2;
+
 template <int W, int ET, int TC>
 struct GridBody {
   using Args = GridArgs;
@@ -226,7 +230,7 @@ __device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint
     char* buf = cbuf[b];
     for (int k = 0; k < n; ++k) {
       const int src = __builtin_amdgcn_readlane(srcv, k);
-      if constexpr (ET == SAR_ECHO_C64) {
+      if constexpr (ET != SAR_ECHO_F16X2) {
         const float* row = (const float*)a.echo + (int64_t)src * a.nf * 2;
         if (FPL == 2 && quad_ok) {
           // one 16-byte load per lane covers the 128 frequencies (2 per lane)
@@ -296,7 +300,7 @@ __device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint
         bk[u] = readlane_f64(beta0, k + u);
 #pragma unroll
         for (int h = 0; h < FPL; ++h) {
-          if constexpr (ET == SAR_ECHO_C64) {
+          if constexpr (ET != SAR_ECHO_F16X2) {
             t2[u][h] = *(const float2*)(buf + (k + u) * EB + h * EBH + lane * 8);
           } else {
             const float2 w2 = __half22float2(*(const __half2*)(buf + (k + u) * EB + h * 256 + lane * 4));
@@ -308,7 +312,11 @@ __device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint
       for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int h = 0; h < FPL; ++h)
-          *(float2*)(buf + (k + u) * EB + h * EBH + lane * 8) = cmul(t2[u][h], cis_cycles(bk[u] * fcc[h]));
+          if constexpr (ET == kEchoC64Fp32Args)
+            *(float2*)(buf + (k + u) * EB + h * EBH + lane * 8) =
+                cmul(t2[u][h], cis_cycles_f32((float)bk[u] * (float)fcc[h]));
+          else
+            *(float2*)(buf + (k + u) * EB + h * EBH + lane * 8) = cmul(t2[u][h], cis_cycles(bk[u] * fcc[h]));
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -479,6 +487,11 @@ sar_status grid_w(const Plan& p, const void* d_echo, float echo_scale, const Wor
   a.nty = p.my / TY;
   const int nfc = (p.nf + 64 * FPL - 1) / (64 * FPL);
   const int64_t nblk = (int64_t)a.ntx * a.nty * nfc;
+  if (p.flags & SAR_FP32_ARGS) {  // precision diagnostic, compiled for W = 4 only
+    if constexpr (W == 4)
+      return launch_body<GridBody<W, kEchoC64Fp32Args, TC>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
+    return fail(SAR_ERR_UNSUPPORTED, "SAR_FP32_ARGS is compiled for a 4-tap lateral kernel");
+  }
   if (p.echo_type == SAR_ECHO_C64)
     return launch_body<GridBody<W, SAR_ECHO_C64, TC>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
   return launch_body<GridBody<W, SAR_ECHO_F16X2, TC>>(sink, (uint32_t)nblk, 0, a, "gridding launch");

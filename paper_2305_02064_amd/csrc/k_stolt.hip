@@ -66,15 +66,17 @@ __device__ __forceinline__ double sqrt_pos(double x) {
   return s;
 }
 
-template <int MZ, int WZ>
+// F32: the precision diagnostic (k_z, its pre-phase and grid position in
+// float32 instead of float64)
+template <int MZ, int WZ, bool F32>
 struct StoltBody {
   using Args = StoltArgs;
   static constexpr int kThreads = 64 * kWaves;
   static __device__ __forceinline__ void run(const StoltArgs& a, uint32_t blk, uint32_t nblk);
 };
 
-template <int MZ, int WZ>
-__device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint32_t blk, uint32_t nblk) {
+template <int MZ, int WZ, bool F32>
+__device__ __forceinline__ void StoltBody<MZ, WZ, F32>::run(const StoltArgs& a, uint32_t blk, uint32_t nblk) {
   constexpr int L2 = MZ / kG;       // points per lane in the first FFT pass
   constexpr int WWIN = WZ + 2;      // register window of cells per lane
   constexpr int RB = 8;             // samples per lane whose loads are in flight together
@@ -135,6 +137,9 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
       const double kx = (double)(P - a.nx / 2) * a.dkx;
       const double ky = (double)(Q - a.ny / 2) * a.dky;
       const double kp2 = kx * kx + ky * ky;
+      const float kxf = (float)(P - a.nx / 2) * (float)a.dkx;
+      const float kyf = (float)(Q - a.ny / 2) * (float)a.dky;
+      const float kp2f = kxf * kxf + kyf * kyf;
       const float sgn = ((P + Q) & 1) ? -1.f : 1.f;
       float2 win[WWIN];
 #pragma unroll
@@ -157,13 +162,26 @@ __device__ __forceinline__ void StoltBody<MZ, WZ>::run(const StoltArgs& a, uint3
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           if (!((valid >> r) & 1u)) continue;
-          const double k = kb[r];
-          const double kz2 = 4.0 * k * k - kp2;
-          if (kz2 <= 0.0) continue;
-          const double kz = sqrt_pos(kz2);
-          const float2 ph = cis_cycles(kz * a.zmid_minus_zref_cyc);
-          const float2 v = cscale(cmul(sb[r], ph), (float)kz * sgn);
-          const double gc = kz * a.dz_cells;  // grid position (cells), not wrapped
+          float kzs;   // k_z for the filter factor
+          float2 ph;   // pre-phase exp(j k_z (z_mid - Z_0))
+          double gc;   // grid position (cells), not wrapped
+          if constexpr (F32) {
+            const float k = (float)kb[r];
+            const float kz2 = 4.f * k * k - kp2f;
+            if (!(kz2 > 0.f)) continue;
+            kzs = __builtin_sqrtf(kz2);
+            ph = cis_cycles_f32(kzs * (float)a.zmid_minus_zref_cyc);
+            gc = (double)(kzs * (float)a.dz_cells);
+          } else {
+            const double k = kb[r];
+            const double kz2 = 4.0 * k * k - kp2;
+            if (kz2 <= 0.0) continue;
+            const double kz = sqrt_pos(kz2);
+            kzs = (float)kz;
+            ph = cis_cycles(kz * a.zmid_minus_zref_cyc);
+            gc = kz * a.dz_cells;
+          }
+          const float2 v = cscale(cmul(sb[r], ph), kzs * sgn);
           const int c0 = (int)floor(gc - 0.5 * WZ) + 1;
           if (!open || c0 < wb || c0 + WZ > wb + WWIN) {
             if (open) flush();
@@ -283,9 +301,14 @@ sar_status stolt_mz(const Plan& p, const StoltArgs& a, LaunchSink& sink) {
   // hardware queue balances the uneven work of central and evanescent columns
   const int64_t ngroups = (a.ncol + kCols - 1) / kCols;
   const int64_t nblk = ngroups < 256 * 72 ? ngroups : 256 * 72;
+  const bool f32 = (p.flags & SAR_FP32_ARGS) != 0;
   switch (p.wz) {
-    case 6: return launch_body<StoltBody<MZ, 6>>(sink, (uint32_t)nblk, 0, a, "stolt launch");
-    case 8: return launch_body<StoltBody<MZ, 8>>(sink, (uint32_t)nblk, 0, a, "stolt launch");
+    case 6:
+      return f32 ? launch_body<StoltBody<MZ, 6, true>>(sink, (uint32_t)nblk, 0, a, "stolt launch")
+                 : launch_body<StoltBody<MZ, 6, false>>(sink, (uint32_t)nblk, 0, a, "stolt launch");
+    case 8:
+      return f32 ? launch_body<StoltBody<MZ, 8, true>>(sink, (uint32_t)nblk, 0, a, "stolt launch")
+                 : launch_body<StoltBody<MZ, 8, false>>(sink, (uint32_t)nblk, 0, a, "stolt launch");
     default: return fail(SAR_ERR_UNSUPPORTED, "Stolt kernel width not compiled");
   }
 }

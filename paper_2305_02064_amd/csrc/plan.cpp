@@ -149,7 +149,9 @@ sar_status validate_desc(const sar_plan_desc* d) {
     return fail(SAR_ERR_UNSUPPORTED, "upsample must be 0 or in [2, 4]");
   if (!(d->kernel_width == 0 || (d->kernel_width >= 3 && d->kernel_width <= kMaxWidth)))
     return fail(SAR_ERR_INVALID, "kernel_width must be 0 or 3..8");
-  if (d->flags & ~SAR_NO_COMPENSATION) return fail(SAR_ERR_INVALID, "unknown flag bits");
+  if (d->flags & ~(SAR_NO_COMPENSATION | SAR_FP32_ARGS)) return fail(SAR_ERR_INVALID, "unknown flag bits");
+  if ((d->flags & SAR_FP32_ARGS) && (d->echo_type != SAR_ECHO_C64 || (d->kernel_width != 0 && d->kernel_width != 4)))
+    return fail(SAR_ERR_UNSUPPORTED, "SAR_FP32_ARGS is compiled for complex64 echo and a 4-tap lateral kernel");
   if (!(d->n_slabs == 0 || d->n_slabs == 1 || (d->n_slabs > 1 && is_pow2(d->n_slabs) && d->n_slabs <= d->nz)))
     return fail(SAR_ERR_INVALID, "n_slabs must be 0, 1 or a power of two that divides nz");
   return SAR_OK;
@@ -201,6 +203,8 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
         break;
       }
   }
+  if ((p.flags & SAR_FP32_ARGS) && (p.w != 4 || p.echo_type != SAR_ECHO_C64))
+    return fail(SAR_ERR_UNSUPPORTED, "SAR_FP32_ARGS is compiled for complex64 echo and a 4-tap lateral kernel");
   // shape parameter of Beatty, Nishimura and Pauly (2005)
   {
     const double a = (p.w / sigma) * (sigma - 0.5);

@@ -31,6 +31,7 @@ STATUS_NAMES = {0: "SAR_OK", 1: "SAR_ERR_INVALID", 2: "SAR_ERR_NOMEM", 3: "SAR_E
 SAR_ECHO_C64 = 0
 SAR_ECHO_F16X2 = 1
 SAR_NO_COMPENSATION = 0x1
+SAR_FP32_ARGS = 0x2
 SAR_BATCH_NO_GRAPH = 0x1
 
 STAGES = ("geometry+sort", "gridding", "fft_x", "fft_y", "stolt", "ifft_y", "ifft_x")

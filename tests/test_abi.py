@@ -70,6 +70,15 @@ def test_descriptor_validation(bad, needle):
     assert needle in str(ei.value)
 
 
+@pytest.mark.parametrize("bad", [dict(kernel_width=6), dict(echo_type=1)])
+def test_fp32_args_diagnostic_limits(bad):
+    sar = _sar()
+    with pytest.raises(sar.SarError) as ei:
+        sar.sar_plan_create(**_desc_kwargs(flags=sar.SAR_FP32_ARGS, **bad))
+    assert ei.value.status == sar.SAR_ERR_UNSUPPORTED
+    assert "SAR_FP32_ARGS" in str(ei.value)
+
+
 def test_upsample_out_of_range_is_unsupported():
     sar = _sar()
     with pytest.raises(sar.SarError) as ei:

@@ -3,7 +3,11 @@ per-scan scale, max(|Re|, |Im|) mapped to 2^15, FP64 phase arguments and grid
 offsets in both) against the FP64 oracle, on the tiny scan (whole image) and
 on the large freehand scan (whole z planes of a sparse-echo image).  Reports
 relative L2 error and the peak-voxel offset (0 = exact) per setting; both
-settings must meet the method's bar of 1e-3 with an exact peak."""
+settings must meet the method's bar of 1e-3 with an exact peak.
+
+A third, diagnostic setting (SAR_FP32_ARGS: FP32 echo with the phase
+arguments and grid offsets in FP32 too) is reported beside them; it is held to
+ten times the bar, since it is not a setting of the method."""
 
 import numpy as np
 import pytest
@@ -31,19 +35,31 @@ def _peak_offset(img, ref):
     return int(np.abs(a - b).max())
 
 
-@pytest.mark.parametrize("setting", ["fp32-echo", "fp16-echo"])
-def test_precision_tiny_scan(torch_cuda, setting):
+def _plan_for(scan, setting):
     from paper_2305_02064_amd import sar
+    if setting == "fp16-echo":
+        return make_plan(scan, echo_type=sar.SAR_ECHO_F16X2)
+    if setting == "fp32-args":
+        return make_plan(scan, flags=sar.SAR_FP32_ARGS)
+    return make_plan(scan)
+
+
+def _bound(setting):
+    return 10 * TOL if setting == "fp32-args" else TOL
+
+
+@pytest.mark.parametrize("setting", ["fp32-echo", "fp16-echo", "fp32-args"])
+def test_precision_tiny_scan(torch_cuda, setting):
     scan = config1_scan(0)
     ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, scan.grid)
     half = setting == "fp16-echo"
-    plan = make_plan(scan, echo_type=sar.SAR_ECHO_F16X2 if half else sar.SAR_ECHO_C64)
+    plan = _plan_for(scan, setting)
     pos, echo, scale = to_device(scan, half=half)
     img = plan.reconstruct(pos, echo, echo_scale=scale).cpu().numpy()
     err = rel_l2(img, ref)
     off = _peak_offset(img, ref)
     print(f"precision tiny {setting}: rel-L2 {err:.3e}, peak offset {off} voxels")
-    assert err <= TOL
+    assert err <= _bound(setting)
     assert peak_ok(img, ref)
 
 
@@ -66,18 +82,17 @@ def big_sparse(torch_cuda):
     return scan, w_list, ref
 
 
-@pytest.mark.parametrize("setting", ["fp32-echo", "fp16-echo"])
+@pytest.mark.parametrize("setting", ["fp32-echo", "fp16-echo", "fp32-args"])
 def test_precision_large_scan_planes(big_sparse, setting):
-    from paper_2305_02064_amd import sar
     scan, w_list, ref = big_sparse
     half = setting == "fp16-echo"
-    plan = make_plan(scan, echo_type=sar.SAR_ECHO_F16X2 if half else sar.SAR_ECHO_C64)
+    plan = _plan_for(scan, setting)
     pos, echo, scale = to_device(scan, half=half)
     img = plan.reconstruct(pos, echo, echo_scale=scale)[:, :, w_list].cpu().numpy()
     err = rel_l2(img, ref)
     offs = [_peak_offset(img[:, :, j], ref[:, :, j]) for j in range(len(w_list))]
     print(f"precision large {setting}: planes {w_list} rel-L2 {err:.3e}, per-plane peak offsets {offs}")
     plan.close()
-    assert err <= TOL
+    assert err <= _bound(setting)
     for j in range(len(w_list)):
         assert peak_ok(img[:, :, j], ref[:, :, j])
