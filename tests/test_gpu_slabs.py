@@ -5,8 +5,9 @@ Checked against the FP64 oracle's reconstruct_slabs (each slab is the direct
 reconstruction of its planes compensated with the slab's own reference depth):
 relative L2 <= 1e-3 with the exact peak voxel, on the wide-baseline two-depth
 scene and on the tiny freehand scan.  Also: the slabs refocus the near target
-of the two-depth scene as in the oracle; a slab plan inside a fused batch
-equals the plain call; a depth-slab plan refuses the single-spectrum calls.
+of the two-depth scene as in the oracle; a slab plan inside a fused batch,
+and served beside a single-depth plan, equals the plain call; a depth-slab
+plan refuses the single-spectrum calls.
 """
 
 import numpy as np
@@ -120,3 +121,27 @@ def test_slab_plan_refuses_single_spectrum_calls(torch_cuda):
         assert ei.value.status == sar.SAR_ERR_UNSUPPORTED
     finally:
         plan.close()
+
+
+def test_slab_plan_served_equals_plain(torch_cuda):
+    # a depth-slab plan and a single-depth one submitted together to a server
+    from paper_2305_02064_amd import sar
+    scans = [depth_pair_scan(), config1_scan(0)]
+    plans = [_plan(scans[0], n_slabs=4), _plan(scans[1])]
+    dev = [to_device(sc) for sc in scans]
+    srv = sar.Server(4 << 30)
+    try:
+        refs = [p.reconstruct(d[0], d[1]).clone() for p, d in zip(plans, dev)]
+        imgs = [p.new_image() for p in plans]
+        # the server runs on its own streams: finish the plain calls first (a
+        # buffer they freed may back one of the served images)
+        torch_cuda.cuda.synchronize()
+        tickets = [srv.submit(p, d[0], d[1], img) for p, d, img in zip(plans, dev, imgs)]
+        for t in tickets:
+            srv.wait(t)
+        for k, (img, ref) in enumerate(zip(imgs, refs)):
+            assert rel_l2(img.cpu().numpy(), ref.cpu().numpy()) <= 1e-6, k
+    finally:
+        srv.close()
+        for p in plans:
+            p.close()
