@@ -153,6 +153,7 @@ sar_status run_back(const Plan& p, const float2* spec, void* d_image, const Work
   gx.sign = +1;
   gx.scale = p.d_signx;
   gx.tw = p.d_tw_nx;
+  gx.nt_out = 1;  // the image: not read again by this library
   if ((st = launch_fft_lines(gx, sink)) != SAR_OK) return st;
   if (tm) tm->mark(first_mark + 3);
   return SAR_OK;

@@ -35,6 +35,18 @@ __device__ __forceinline__ float2 cis_cycles(double t) {
   const float r = (float)fr;
   return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
 }
+// streaming (non-temporal) loads and stores of one complex value: lines read or
+// written once are marked for early eviction instead of displacing reused ones
+typedef float f2_vec __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  const f2_vec v = __builtin_nontemporal_load((const f2_vec*)p);
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void store_stream(float2* p, float2 v) {
+  const f2_vec w = {v.x, v.y};
+  __builtin_nontemporal_store(w, (f2_vec*)p);
+}
+
 // the same with the argument formed and reduced in float32 (precision diagnostic)
 __device__ __forceinline__ float2 cis_cycles_f32(float t) {
   const float r = __builtin_amdgcn_fractf(t);

@@ -10,7 +10,10 @@
 // exchanges through LDS once, and finishes with an L1-point register DFT.
 // A block handles BC adjacent batch columns so loads and stores move BC*8
 // contiguous bytes per row.  The epilogue fuses the crop to the image's
-// centred modes and a per-output scale (deapodisation or +-1 signs).
+// centred modes and a per-output scale (deapodisation or +-1 signs).  Inputs
+// are read once, with streaming loads; outputs use streaming stores only where
+// no later kernel reads them soon (the image), since the next pass reads the
+// others straight back.
 
 #include "device_common.hpp"
 #include "launch.hpp"
@@ -47,7 +50,7 @@ __device__ __forceinline__ void FftBody<L1, L2, BC, SIGN>::run(const FftLines& a
     float2 v[L2];
 #pragma unroll
     for (int l2 = 0; l2 < L2; ++l2)
-      v[l2] = bv ? in[(int64_t)(t + L1 * l2) * a.s_in_l] : make_float2(0.f, 0.f);
+      v[l2] = bv ? load_stream(&in[(int64_t)(t + L1 * l2) * a.s_in_l]) : make_float2(0.f, 0.f);
     reg_dft_dif<L2, SIGN>(v);
     static_for<0, L2>([&](auto kc) __attribute__((always_inline)) {
       constexpr int k2 = decltype(kc)::value;
@@ -77,7 +80,10 @@ __device__ __forceinline__ void FftBody<L1, L2, BC, SIGN>::run(const FftLines& a
         if (P >= 0) {
           float2 y = v[ct_bitrev(k1, ct_log2(L1))];
           if (a.scale) y = cscale(y, a.scale[P]);
-          out[(int64_t)P * a.s_out_k] = y;
+          if (a.nt_out)
+            store_stream(&out[(int64_t)P * a.s_out_k], y);
+          else
+            out[(int64_t)P * a.s_out_k] = y;
         }
       });
     }

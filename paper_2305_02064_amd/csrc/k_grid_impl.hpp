@@ -461,7 +461,7 @@ __device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint
       for (int r = 0; r < TY; ++r)
 #pragma unroll
         for (int c = 0; c < TX; ++c)
-          a.grid[((int64_t)(ty0 + r) * a.mx + (tx0 + c)) * a.nf + fq[h]] = acc[r][c][h];
+          store_stream(&a.grid[((int64_t)(ty0 + r) * a.mx + (tx0 + c)) * a.nf + fq[h]], acc[r][c][h]);
     }
   }
 }

@@ -124,6 +124,7 @@ struct FftLines {
   int sign;  // -1 forward, +1 inverse
   const float* scale;
   const float2* tw;  // exp(sign j 2 pi i / L), i < L
+  int nt_out;        // non-temporal stores (an output no later kernel reads soon)
 };
 sar_status launch_fft_lines(const FftLines& a, LaunchSink& sink);
 sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, LaunchSink& sink);
