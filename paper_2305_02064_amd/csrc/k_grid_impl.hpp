@@ -14,7 +14,8 @@
 // sample's cell offset (A, B) relative to the tile; a uniform binary dispatch
 // selects a fully unrolled body for that offset, so every accumulator index is
 // static.  Tiles partition the grid, so each cell is written exactly once with
-// plain coalesced stores: no atomics, no zeroing pass, a fixed summation order.
+// coalesced streaming stores (marked for early eviction, so they do not push
+// echo rows out of L2): no atomics, no zeroing pass, a fixed summation order.
 //
 // Echo rows are streamed through LDS in chunks of 8 samples with the direct
 // global-to-LDS loads of gfx950: at the start of chunk c the wave waits once,
