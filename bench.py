@@ -177,7 +177,7 @@ def oracle_uneven(n_small=8, n_random=4, full_macs=1.2e11, seed=0):
             "selection": f"{n_small} cheapest of the 64 uneven-batch scans plus {n_random} others (seed {seed})"}
 
 
-def serving_bench(big_scan, big_pos, big_plan, n_requests, rates, seed=0):
+def serving_bench(big_scan, big_pos, big_plan, n_requests, rates, host_rates=(), seed=0):
     """Served vs plain per-scan path on a stream of scans shaped like the
     serving workload: 95% scans of the uneven batch (64 distinct scans, side
     64-256 positions, 64-256 frequencies), 5% scans of the large freehand size.
@@ -342,6 +342,71 @@ def serving_bench(big_scan, big_pos, big_plan, n_requests, rates, seed=0):
         t_s = time.perf_counter() - t0
         out["poisson"].append({"rate_per_s": rate, "plain": {"scans_per_s": n_requests / t_p, **pct(lat_p)},
                                "served": {"scans_per_s": n_requests / t_s, **pct(lat_s)}})
+    # the same Poisson streams with every request's positions and echo starting
+    # in pinned host memory (uploads counted in the latency).  Plain: each
+    # arrival copies its inputs to the device on the one stream, then
+    # reconstructs; served: the host tensors go to sar_submit, which stages the
+    # uploads itself.
+    if host_rates:
+        hin = {i: (distinct[i][1].cpu().pin_memory(), distinct[i][2].cpu().pin_memory()) for i in set(seq)}
+        mean_up = sum(hin[i][0].numel() * 8 + hin[i][1].numel() * 8 for i in seq) / n_requests
+        out["poisson_host_input"] = {"mean_upload_bytes": mean_up, "rates": []}
+        for rate in host_rates:
+            arr = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+            pending = []
+            lat_p = []
+
+            def retire_h(t0):
+                keep = []
+                for a, e in pending:
+                    if e.query():
+                        lat_p.append(time.perf_counter() - t0 - a)
+                    else:
+                        keep.append((a, e))
+                pending[:] = keep
+
+            t0 = time.perf_counter()
+            for k, i in enumerate(seq):
+                while time.perf_counter() - t0 < arr[k]:
+                    retire_h(t0)
+                distinct[i][1].copy_(hin[i][0], non_blocking=True)
+                distinct[i][2].copy_(hin[i][1], non_blocking=True)
+                plain_one(i)
+                e = torch.cuda.Event()
+                e.record(stream)
+                pending.append((arr[k], e))
+                if k % 500 == 499:
+                    print(f"poisson host-fed {rate}/s plain: {k + 1} of {n_requests} submitted", file=sys.stderr,
+                          flush=True)
+            while pending:
+                retire_h(t0)
+            t_p = time.perf_counter() - t0
+            lat_s = []
+            live = []
+            t0 = time.perf_counter()
+            for k, i in enumerate(seq):
+                while time.perf_counter() - t0 < arr[k]:
+                    still = []
+                    for t in live:
+                        done, lat, _ = srv.poll(t)
+                        if done:
+                            lat_s.append(lat)
+                        else:
+                            still.append(t)
+                    live = still
+                live.append(srv.submit(distinct[i][0], hin[i][0], hin[i][1], images[i]))
+                if k % 500 == 499:
+                    print(f"poisson host-fed {rate}/s served: {k + 1} of {n_requests} submitted", file=sys.stderr,
+                          flush=True)
+            for t in live:
+                lat_s.append(srv.wait(t)[0])
+            t_s = time.perf_counter() - t0
+            out["poisson_host_input"]["rates"].append({
+                "rate_per_s": rate, "offered_GB_per_s": rate * mean_up / 1e9,
+                "plain": {"scans_per_s": n_requests / t_p, **pct(lat_p)},
+                "served": {"scans_per_s": n_requests / t_s, **pct(lat_s)}})
+        del hin
+
     # echoes starting in pinned host memory (uploads counted): the 16 smallest
     # uneven scans, 64 requests, all submitted at once
     small = sorted(range(64), key=lambda i: distinct[i][2].numel())[:16]
@@ -436,6 +501,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the tiny-scan comparison and the serving runs")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-rates", type=str, default="50,200,500")
+    ap.add_argument("--serve-host-rates", type=str, default="",
+                    help="Poisson rates for a sweep with every request's inputs in pinned host memory (opt-in)")
     ap.add_argument("--oracle-uneven", action="store_true",
                     help="also time the FP64 oracle beside the GPU on 12 scans of the uneven batch (minutes of CPU)")
     args = ap.parse_args()
@@ -529,7 +596,8 @@ def main():
     if not args.no_serving:
         out["comparison_tiny"] = comparison_tiny()
         out["serving"] = serving_bench(scan, pos, plan, args.serve_requests,
-                                       [float(r) for r in args.serve_rates.split(",") if r])
+                                       [float(r) for r in args.serve_rates.split(",") if r],
+                                       [float(r) for r in args.serve_host_rates.split(",") if r])
     if not args.no_cpu_baseline:
         def echo_host(kk):
             return echo[:, :, :kk].cpu().numpy().astype(np.complex128)
