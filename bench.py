@@ -559,6 +559,19 @@ def main():
     alg_bytes = n_v * nf * 8 + info["mx"] * info["my"] * nf * 8 + n_v * rec_bytes
     achieved = alg_bytes / (grid_avg_ms * 1e-3) / 1e9
     traffic = recorded_traffic()
+    # a plain device copy of 1 GiB for context: what the memory system gives a
+    # perfectly streaming kernel (read + write bytes over time)
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbps = 10 * 2 * src.numel() * 4 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
     out = {
         "metric": METRIC,
         "value": voxels / (ms_per_step * 1e-3),
@@ -590,6 +603,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "algorithmic_bytes_per_launch": alg_bytes,
+            "measured_copy_GB_per_s": copy_gbps,
         },
         "input_generation_s": t_gen,
     }
