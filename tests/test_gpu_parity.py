@@ -136,6 +136,22 @@ def test_largest_transform_lengths(torch_cuda, nx, ny):
     assert err <= IMAGE_TOL
 
 
+def test_long_sweep(torch_cuda):
+    # 700 frequencies: each Stolt lane's run spans several load batches with a
+    # partial last one, and the gridding's frequency chunks end mid-wave
+    grid = ImageGrid(nx=16, ny=16, nz=8, x0=-0.008, y0=-0.008, z0=0.25, dx=1e-3, dy=1e-3, dz=0.01,
+                     z_ref=0.0, z_focus=0.3)
+    scan = _ragged_scan(91, 61, 700, grid)
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, grid)
+    plan = make_plan(scan)
+    pos, echo, _ = to_device(scan)
+    img = plan.reconstruct(pos, echo).cpu().numpy()
+    plan.close()
+    err = rel_l2(img, ref)
+    print(f"700-frequency sweep: image rel-L2 {err:.3e}")
+    assert err <= IMAGE_TOL
+
+
 def test_no_compensation_flag(torch_cuda, tiny):
     from paper_2305_02064_amd import sar
     scan, _, _ = tiny
