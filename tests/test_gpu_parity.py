@@ -152,6 +152,31 @@ def test_long_sweep(torch_cuda):
     assert err <= IMAGE_TOL
 
 
+@pytest.mark.parametrize("n_pos", [1, 37])
+def test_other_array_layout(torch_cuda, n_pos):
+    # 3 Tx x 5 Rx at irregular offsets (15 pairs, pair = t * 5 + r), one shot or
+    # a few: the pair tables and the virtual-sample indexing beyond 2 x 4
+    from sarsynth import Scan
+    rng = np.random.default_rng(300 + n_pos)
+    tx = rng.uniform(-0.01, 0.01, (3, 2))
+    rx = rng.uniform(-0.01, 0.01, (5, 2))
+    grid = ImageGrid(nx=16, ny=16, nz=8, x0=-0.008, y0=-0.008, z0=0.25, dx=1e-3, dy=1e-3, dz=0.01,
+                     z_ref=0.0, z_focus=0.3)
+    pos = np.stack([rng.uniform(-0.01, 0.01, n_pos), rng.uniform(-0.01, 0.01, n_pos),
+                    rng.uniform(-0.005, 0.005, n_pos)], 1)
+    nf = 24
+    echo = (rng.standard_normal((n_pos, 15, nf)) + 1j * rng.standard_normal((n_pos, 15, nf))).astype(np.complex64)
+    scan = Scan(pos=pos, tx_xy=tx, rx_xy=rx, freq=sweep(nf), grid=grid, echo=echo)
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, grid)
+    plan = make_plan(scan)
+    pos_d, echo_d, _ = to_device(scan)
+    img = plan.reconstruct(pos_d, echo_d).cpu().numpy()
+    plan.close()
+    err = rel_l2(img, ref)
+    print(f"3 x 5 array, {n_pos} shots: image rel-L2 {err:.3e}")
+    assert err <= IMAGE_TOL
+
+
 def test_no_compensation_flag(torch_cuda, tiny):
     from paper_2305_02064_amd import sar
     scan, _, _ = tiny
