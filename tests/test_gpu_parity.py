@@ -177,6 +177,22 @@ def test_other_array_layout(torch_cuda, n_pos):
     assert err <= IMAGE_TOL
 
 
+def test_single_frequency(torch_cuda):
+    # a one-frequency sweep (a single-frequency hologram): one valid lane per
+    # gridding frequency chunk, one sample per Stolt column
+    grid = ImageGrid(nx=16, ny=16, nz=4, x0=-0.008, y0=-0.008, z0=0.25, dx=1e-3, dy=1e-3, dz=0.01,
+                     z_ref=0.0, z_focus=0.3)
+    scan = _ragged_scan(97, 45, 1, grid)
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, grid)
+    plan = make_plan(scan)
+    pos, echo, _ = to_device(scan)
+    img = plan.reconstruct(pos, echo).cpu().numpy()
+    plan.close()
+    err = rel_l2(img, ref)
+    print(f"single-frequency sweep: image rel-L2 {err:.3e}")
+    assert err <= IMAGE_TOL
+
+
 def test_no_compensation_flag(torch_cuda, tiny):
     from paper_2305_02064_amd import sar
     scan, _, _ = tiny
