@@ -6,7 +6,8 @@
 //   X[k2 + L2 k1] = sum_{l1} w_L1^{l1 k1} w_L^{l1 k2} sum_{l2} x[l1 + L1 l2] w_L2^{l2 k2}:
 // each thread loads one stride-L1 subsequence of one batch column straight
 // from HBM into registers, runs an unrolled L2-point DFT with compile-time
-// twiddles, applies the inter-step twiddle from a float64-generated table,
+// twiddles, applies the inter-step twiddle (built from two entries of a
+// float64-generated table),
 // exchanges through LDS once, and finishes with an L1-point register DFT.
 // A block handles BC adjacent batch columns so loads and stores move BC*8
 // contiguous bytes per row.  The epilogue fuses the crop to the image's
@@ -52,10 +53,26 @@ __device__ __forceinline__ void FftBody<L1, L2, BC, SIGN>::run(const FftLines& a
     for (int l2 = 0; l2 < L2; ++l2)
       v[l2] = bv ? load_stream(&in[(int64_t)(t + L1 * l2) * a.s_in_l]) : make_float2(0.f, 0.f);
     reg_dft_dif<L2, SIGN>(v);
+    // inter-step twiddles w_L^(t k2) from two table reads, w^t and w^(TB t):
+    // w^(t k2) = (w^(TB t))^(k2 / TB) (w^t)^(k2 % TB), at most about nine
+    // roundings each (the table reads they replace were a third of the
+    // pass's memory instructions)
+    constexpr int TB = L2 < 8 ? L2 : 8;
+    float2 p1[TB], pB[(L2 + TB - 1) / TB];
+    p1[0] = make_float2(1.f, 0.f);
+    pB[0] = make_float2(1.f, 0.f);
+    {
+      const float2 w1 = a.tw[t];
+#pragma unroll
+      for (int j = 1; j < TB; ++j) p1[j] = cmul(p1[j - 1], w1);
+      const float2 wB = a.tw[(TB * t) % L];
+#pragma unroll
+      for (int j = 1; j < (L2 + TB - 1) / TB; ++j) pB[j] = cmul(pB[j - 1], wB);
+    }
     static_for<0, L2>([&](auto kc) __attribute__((always_inline)) {
       constexpr int k2 = decltype(kc)::value;
       float2 y = v[ct_bitrev(k2, ct_log2(L2))];
-      if constexpr (k2 != 0) y = cmul(y, a.tw[t * k2]);
+      if constexpr (k2 != 0) y = cmul(y, cmul(pB[k2 / TB], p1[k2 % TB]));
       lds[t * RS + k2 * BC + b] = y;
     });
   }
