@@ -209,10 +209,25 @@ __device__ __forceinline__ void StoltBody<MZ, WZ, F32>::run(const StoltArgs& a, 
     for (int l2 = 0; l2 < L2; ++l2) v1[l2] = g[gl + kG * l2];
     reg_dft_dif<L2, +1>(v1);
     __syncthreads();
+    // twiddles w_MZ^(l1 k2) from two table entries, w^l1 and w^(TB l1), and
+    // their powers (at most about nine roundings each) instead of one table
+    // read per k2
+    constexpr int TB = L2 < 8 ? L2 : 8;
+    float2 p1[TB], pB[(L2 + TB - 1) / TB];
+    p1[0] = make_float2(1.f, 0.f);
+    pB[0] = make_float2(1.f, 0.f);
+    {
+      const float2 w1 = tw[gl];
+#pragma unroll
+      for (int j = 1; j < TB; ++j) p1[j] = cmul(p1[j - 1], w1);
+      const float2 wB = tw[(TB * gl) % MZ];
+#pragma unroll
+      for (int j = 1; j < (L2 + TB - 1) / TB; ++j) pB[j] = cmul(pB[j - 1], wB);
+    }
     static_for<0, L2>([&](auto kc) __attribute__((always_inline)) {
       constexpr int k2 = decltype(kc)::value;
       float2 y = v1[ct_bitrev(k2, ct_log2(L2))];
-      if constexpr (k2 != 0) y = cmul(y, tw[gl * k2]);
+      if constexpr (k2 != 0) y = cmul(y, cmul(pB[k2 / TB], p1[k2 % TB]));
       g[gl * (L2 + 1) + k2] = y;   // [l1][k2], padded rows
     });
     __syncthreads();
