@@ -81,6 +81,12 @@ typedef enum { SAR_ECHO_C64 = 0, SAR_ECHO_F16X2 = 1 } sar_echo_type;
  * measure what the float64 arguments buy.  Needs complex64 echo and a 4-tap
  * lateral kernel (SAR_ERR_UNSUPPORTED otherwise). */
 #define SAR_FP32_ARGS 0x2u
+/* Stolt density compensation: the filter of Eq. (15) is further multiplied by
+ * the Jacobian of the change of variables from k to k_z, dk_z/dk = 4k / k_z
+ * (from Eq. (14) at fixed k_x, k_y), so the sum over frequency of step a5
+ * weights each sample by the k_z interval it covers.  The paper states only
+ * the k_z factor; off by default. */
+#define SAR_STOLT_DCF 0x4u
 
 /* Plan descriptor: array geometry, frequency sweep and image grid.
  * Constraints (SAR_ERR_INVALID otherwise):
@@ -150,6 +156,13 @@ typedef struct {
   int32_t grid_tile_x, grid_tile_y;  /* its cells per wave along x and y */
   int32_t grid_freqs_per_lane;       /* its frequencies per lane (64 lanes per wave) */
   int32_t n_slabs;       /* depth slabs (1: one reference depth) */
+  /* the descriptor's sizes as the plan keeps them */
+  int32_t nx, ny, nz;
+  int32_t n_freq;
+  int32_t echo_type;     /* sar_echo_type */
+  uint32_t flags;
+  int64_t max_pos;
+  double sigma_x, sigma_y;  /* effective lateral oversampling mx / nx, my / ny */
 } sar_plan_info;
 
 /* Create a plan on HIP device `device`: validates the descriptor, chooses the
@@ -159,8 +172,11 @@ typedef struct {
  * Errors: SAR_ERR_INVALID (descriptor), SAR_ERR_NOMEM, SAR_ERR_DEVICE. */
 sar_status sar_plan_create(const sar_plan_desc* desc, int device, sar_plan* out);
 
-/* Release the plan's device tables.  The caller must ensure no work that uses
- * the plan is still queued.  NULL is accepted. */
+/* Release the plan's device tables.  NULL is accepted.  SAR_ERR_BUSY (and
+ * nothing released) while a server request submitted with the plan has not
+ * finished or a batch built from it has not been destroyed.  Work queued on
+ * streams by the caller's own sar_reconstruct / sar_spectrum calls is not
+ * tracked: the caller must ensure it has finished. */
 sar_status sar_plan_destroy(sar_plan plan);
 
 /* Bytes of device workspace sar_reconstruct / sar_spectrum /
@@ -198,7 +214,9 @@ sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* 
  * unit amplitude weight, on the plan's image grid (layouts and arguments as
  * sar_reconstruct; no workspace).  Cost n_pos * n_pair * n_freq * nx*ny*nz:
  * meant for small scans, to compare the fast method's images and times.
- * Asynchronous on `stream`. */
+ * Asynchronous on `stream`.  SAR_ERR_UNSUPPORTED (nothing queued) when
+ * n_pos * n_pair * n_freq * nx * ny * nz exceeds 1e12 terms (about a second of
+ * one MI355X): a single dispatch that long would look like a hang. */
 sar_status sar_backproject(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
                            void* d_image, sar_stream_t stream);
 

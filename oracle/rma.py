@@ -94,9 +94,17 @@ def axial_wavenumber(k, kx, ky):
     return np.sqrt(np.where(mask, kz2, 0.0)), mask
 
 
-def rma_filter(spec, kz, mask, z_ref):
-    """F = S k_z exp(-j k_z Z_0) / P(f), P = 1 (Eq. (15)); evanescent -> 0."""
-    return np.where(mask, spec * kz * np.exp(-1j * kz * float(z_ref)), 0.0)
+def rma_filter(spec, kz, mask, z_ref, k=None, dcf=False):
+    """F = S k_z exp(-j k_z Z_0) / P(f), P = 1 (Eq. (15)); evanescent -> 0.
+
+    dcf=True (the optional Jacobian of the change of variables from k to k_z,
+    on which the paper is silent): F is further multiplied by
+    dk_z/dk = 4 k / k_z, which follows from differentiating Eq. (14) at fixed
+    (k_x, k_y); k [N_f] is then required."""
+    if not dcf:
+        return np.where(mask, spec * kz * np.exp(-1j * kz * float(z_ref)), 0.0)
+    jac = np.where(mask, 4.0 * np.asarray(k)[None, None, :] / np.where(mask, kz, 1.0), 0.0)
+    return np.where(mask, spec * kz * jac * np.exp(-1j * kz * float(z_ref)), 0.0)
 
 
 def stolt_direct(filt, kz, mask, zw):
@@ -142,17 +150,18 @@ def spectrum_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation=True):
     return nudft2(shat, xv, yv, kx, ky, xc, yc)
 
 
-def image_from_spectrum(spec, freq, grid):
-    """Steps 2-4 on a spectrum [N_y, N_x, N_f]; returns the image [N_x, N_y, N_z]."""
+def image_from_spectrum(spec, freq, grid, dcf=False):
+    """Steps 2-4 on a spectrum [N_y, N_x, N_f]; returns the image [N_x, N_y, N_z]
+    (dcf: see rma_filter)."""
     k = wavenumber(freq)
     kx, ky, _, _ = mode_axes(grid.nx, grid.ny, grid.x0, grid.y0, grid.dx, grid.dy)
     kz, mask = axial_wavenumber(k, kx, ky)
-    filt = rma_filter(spec, kz, mask, grid.z_ref)
+    filt = rma_filter(spec, kz, mask, grid.z_ref, k, dcf)
     zw = grid.z0 + grid.dz * np.arange(grid.nz)
     return idft2(stolt_direct(filt, kz, mask, zw))
 
 
-def image_planes_from_spectrum(spec, freq, grid, w_list, row_chunk=16):
+def image_planes_from_spectrum(spec, freq, grid, w_list, row_chunk=16, dcf=False):
     """Steps 2-4 for selected z planes only; returns [N_x, N_y, len(w_list)].
     Chunked over k_y rows so large spectra fit in memory."""
     k = wavenumber(freq)
@@ -162,15 +171,16 @@ def image_planes_from_spectrum(spec, freq, grid, w_list, row_chunk=16):
     for r0 in range(0, grid.ny, row_chunk):
         rs = slice(r0, r0 + row_chunk)
         kz, mask = axial_wavenumber(k, kx, ky[rs])
-        filt = rma_filter(np.asarray(spec[rs], np.complex128), kz, mask, grid.z_ref)
+        filt = rma_filter(np.asarray(spec[rs], np.complex128), kz, mask, grid.z_ref, k, dcf)
         zc[rs] = stolt_direct(filt, kz, mask, zw)
     return idft2(zc)
 
 
-def reconstruct_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation=True):
-    """Full image [N_x, N_y, N_z] of one scan (Fig. 3 pipeline, Eq. (16))."""
+def reconstruct_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation=True, dcf=False):
+    """Full image [N_x, N_y, N_z] of one scan (Fig. 3 pipeline, Eq. (16));
+    dcf: see rma_filter."""
     spec = spectrum_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation)
-    return image_from_spectrum(spec, freq, grid)
+    return image_from_spectrum(spec, freq, grid, dcf)
 
 
 def slab_grids(grid, n_slabs):

@@ -1,6 +1,6 @@
 """Build libsar.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2305_02064_amd.build [--jobs N]
+    python -m paper_2305_02064_amd.build [--jobs N] [--incremental]
 
 Objects go to paper_2305_02064_amd/_build/; the shared library to
 paper_2305_02064_amd/libsar.so.
@@ -31,8 +31,18 @@ COMMON = [
 ]
 
 
-def _compile(src):
+def _newest_header():
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    hs += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src, incremental=False):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _newest_header():
+            return obj
     lang = ["-x", "hip"]
     extra = []
     if src.startswith("k_grid_w"):
@@ -49,11 +59,13 @@ def _compile(src):
     return obj
 
 
-def build(jobs=None, verbose=False):
+def build(jobs=None, verbose=False, incremental=False):
+    """Compile every source (incremental=True: only those older than their
+    object or than any header) and link libsar.so."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, min(8, os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, incremental), SOURCES))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -68,6 +80,8 @@ def build(jobs=None, verbose=False):
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true",
+                    help="recompile only sources older than their object or than a header")
     args = ap.parse_args()
-    build(args.jobs, verbose=True)
+    build(args.jobs, verbose=True, incremental=args.incremental)
     sys.exit(0)

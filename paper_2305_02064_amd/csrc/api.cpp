@@ -242,6 +242,9 @@ sar_status sar_plan_create(const sar_plan_desc* desc, int device, sar_plan* out)
 
 sar_status sar_plan_destroy(sar_plan plan) {
   if (!plan) return SAR_OK;
+  if (plan->p.users.load() > 0)
+    return fail(SAR_ERR_BUSY, "plan is still used by " + std::to_string(plan->p.users.load()) +
+                                  " server request(s) or batch(es)");
   DeviceGuard g(plan->p.device);
   free_plan(plan->p);
   delete plan;
@@ -274,6 +277,15 @@ sar_status sar_plan_get_info(sar_plan plan, sar_plan_info* info) {
   info->grid_tile_y = kGridTiles[p.grid_tile][1];
   info->grid_freqs_per_lane = kGridTiles[p.grid_tile][2];
   info->n_slabs = p.slabs.empty() ? 1 : (int32_t)p.slabs.size();
+  info->nx = p.nx;
+  info->ny = p.ny;
+  info->nz = p.nz;
+  info->n_freq = p.nf;
+  info->echo_type = p.echo_type;
+  info->flags = p.flags;
+  info->max_pos = p.max_pos;
+  info->sigma_x = (double)p.mx / p.nx;
+  info->sigma_y = (double)p.my / p.ny;
   return SAR_OK;
 }
 

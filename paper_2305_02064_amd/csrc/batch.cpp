@@ -273,6 +273,7 @@ sar_status sar_batch_create(const sar_plan* plans, int32_t n, uint32_t flags, sa
     delete h;
     return st;
   }
+  for (sar_plan q : b.plans) q->p.users.fetch_add(1);  // released by sar_batch_destroy
   *out = h;
   return SAR_OK;
 }
@@ -327,6 +328,7 @@ sar_status sar_batch_destroy(sar_batch batch) {
   if (!batch) return SAR_OK;
   DeviceGuard g(batch->s.device);
   release(batch->s);
+  for (sar_plan q : batch->s.plans) q->p.users.fetch_sub(1);
   delete batch;
   return SAR_OK;
 }

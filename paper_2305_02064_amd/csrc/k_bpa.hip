@@ -91,6 +91,10 @@ sar_status launch_backprojection(const Plan& p, const double* d_pos, int64_t n_p
   a.dy = p.dy;
   a.dz = p.dz;
   const int64_t nvox = (int64_t)p.nx * p.ny * p.nz;
+  const double terms = (double)n_pos * p.n_pair * p.nf * (double)nvox;
+  if (terms > kMaxBackprojectionTerms)
+    return fail(SAR_ERR_UNSUPPORTED, "back-projection of " + std::to_string(terms) +
+                                         " terms (samples x frequencies x voxels) exceeds the limit of 1e12");
   return launch_body<BpaBody>(sink, (uint32_t)((nvox + BpaBody::kThreads - 1) / BpaBody::kThreads), 0, a,
                               "back-projection launch");
 }

@@ -4,7 +4,8 @@
 // For every (k_x, k_y) column of the spectrum, each frequency sample f_i
 // becomes a non-uniform sample at k_z = sqrt(4 k_i^2 - k_x^2 - k_y^2)
 // (Eq. (14); evanescent samples are dropped) with value
-// S k_z exp(-j k_z Z_0) (Eq. (15), P = 1).  The Stolt map plus the inverse
+// S k_z exp(-j k_z Z_0) (Eq. (15), P = 1), or S 4k exp(-j k_z Z_0) with the
+// optional Jacobian dk_z/dk = 4k/k_z of the change of variables.  The Stolt map plus the inverse
 // transform along z is the non-uniform sum
 //   Z(z_w) = sum_i F_i exp(+j k_z,i z_w),  z_w = z0 + w dz,
 // a 1-D type-1 NUFFT at the positions theta_i = k_z,i dz: float64 pre-phase
@@ -42,6 +43,7 @@ struct StoltArgs {
   double zmid_minus_zref_cyc;  // (z_mid - Z_0) / (2 pi)
   double dz_cells;             // dz * MZ / (2 pi)
   float es_beta;
+  int dcf;             // 1: filter factor 4k (k_z times the Jacobian dk_z/dk = 4k/k_z)
   int64_t ncol;
 };
 
@@ -162,7 +164,7 @@ __device__ __forceinline__ void StoltBody<MZ, WZ, F32>::run(const StoltArgs& a, 
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           if (!((valid >> r) & 1u)) continue;
-          float kzs;   // k_z for the filter factor
+          float kzs;   // filter factor: k_z, or 4k with the Jacobian
           float2 ph;   // pre-phase exp(j k_z (z_mid - Z_0))
           double gc;   // grid position (cells), not wrapped
           if constexpr (F32) {
@@ -172,12 +174,13 @@ __device__ __forceinline__ void StoltBody<MZ, WZ, F32>::run(const StoltArgs& a, 
             kzs = __builtin_sqrtf(kz2);
             ph = cis_cycles_f32(kzs * (float)a.zmid_minus_zref_cyc);
             gc = (double)(kzs * (float)a.dz_cells);
+            if (a.dcf) kzs = 4.f * k;
           } else {
             const double k = kb[r];
             const double kz2 = 4.0 * k * k - kp2;
             if (kz2 <= 0.0) continue;
             const double kz = sqrt_pos(kz2);
-            kzs = (float)kz;
+            kzs = a.dcf ? (float)(4.0 * k) : (float)kz;
             ph = cis_cycles(kz * a.zmid_minus_zref_cyc);
             gc = kz * a.dz_cells;
           }
@@ -264,6 +267,7 @@ struct PlaneArgs {
   int nx, ny, nf;
   double dkx, dky;
   double z_cyc;        // (z0 - Z_0) / (2 pi)
+  int dcf;             // 1: filter factor 4k instead of k_z (see StoltArgs)
   int64_t ncol;
 };
 
@@ -293,8 +297,9 @@ struct PlaneBody {
         if (kz2 <= 0.0) continue;
         const double kz = sqrt(kz2);
         const float2 v = cmul(sp[i], cis_cycles(kz * a.z_cyc));
-        acc.x = fmaf(v.x, (float)kz, acc.x);
-        acc.y = fmaf(v.y, (float)kz, acc.y);
+        const float wf = a.dcf ? (float)(4.0 * k) : (float)kz;
+        acc.x = fmaf(v.x, wf, acc.x);
+        acc.y = fmaf(v.y, wf, acc.y);
       }
 #pragma unroll
       for (int m = G / 2; m >= 1; m >>= 1) {
@@ -342,6 +347,7 @@ sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, Launch
     b.dkx = 2.0 * M_PI / (p.nx * p.dx);
     b.dky = 2.0 * M_PI / (p.ny * p.dy);
     b.z_cyc = (p.z0 - p.z_ref) / (2.0 * M_PI);
+    b.dcf = (p.flags & SAR_STOLT_DCF) ? 1 : 0;
     b.ncol = (int64_t)p.nx * p.ny;
     const int64_t ngroups = (b.ncol + 15) / 16;
     const int64_t nblk = ngroups < 256 * 8 ? ngroups : 256 * 8;
@@ -363,6 +369,7 @@ sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, Launch
   a.zmid_minus_zref_cyc = (zmid - p.z_ref) / (2.0 * M_PI);
   a.dz_cells = p.dz * p.mz / (2.0 * M_PI);
   a.es_beta = (float)p.es_beta;
+  a.dcf = (p.flags & SAR_STOLT_DCF) ? 1 : 0;
   a.ncol = (int64_t)p.nx * p.ny;
   if (a.ncol == 0) return SAR_OK;
   switch (p.mz) {

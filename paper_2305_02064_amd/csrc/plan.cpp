@@ -149,7 +149,8 @@ sar_status validate_desc(const sar_plan_desc* d) {
     return fail(SAR_ERR_UNSUPPORTED, "upsample must be 0 or in [2, 4]");
   if (!(d->kernel_width == 0 || (d->kernel_width >= 3 && d->kernel_width <= kMaxWidth)))
     return fail(SAR_ERR_INVALID, "kernel_width must be 0 or 3..8");
-  if (d->flags & ~(SAR_NO_COMPENSATION | SAR_FP32_ARGS)) return fail(SAR_ERR_INVALID, "unknown flag bits");
+  if (d->flags & ~(SAR_NO_COMPENSATION | SAR_FP32_ARGS | SAR_STOLT_DCF))
+    return fail(SAR_ERR_INVALID, "unknown flag bits");
   if ((d->flags & SAR_FP32_ARGS) && (d->echo_type != SAR_ECHO_C64 || (d->kernel_width != 0 && d->kernel_width != 4)))
     return fail(SAR_ERR_UNSUPPORTED, "SAR_FP32_ARGS is compiled for complex64 echo and a 4-tap lateral kernel");
   if (!(d->n_slabs == 0 || d->n_slabs == 1 || (d->n_slabs > 1 && is_pow2(d->n_slabs) && d->n_slabs <= d->nz)))
@@ -192,6 +193,9 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
   const double up = d->upsample > 0 ? d->upsample : 2.0;
   p.mx = next_pow2((int64_t)std::ceil(up * p.nx - 1e-9));
   p.my = next_pow2((int64_t)std::ceil(up * p.ny - 1e-9));
+  if (p.mx > kMaxFftLength || p.my > kMaxFftLength)
+    return fail(SAR_ERR_UNSUPPORTED, "oversampled grid of " + std::to_string(p.mx) + " x " + std::to_string(p.my) +
+                                         " cells: at most " + std::to_string(kMaxFftLength) + " per axis");
   const double sigma = std::min((double)p.mx / p.nx, (double)p.my / p.ny);
   if (d->kernel_width > 0) {
     p.w = d->kernel_width;

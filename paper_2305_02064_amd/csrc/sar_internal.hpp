@@ -3,8 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
-#include <string>
+#include <atomic>
 #include <memory>
+#include <string>
 #include <vector>
 
 #include "sar.h"
@@ -21,6 +22,10 @@ constexpr bool grid_tile_compiled(int tile, int w) {
   return tile >= 0 && tile < kNumGridTiles && w >= kGridTileWidths[tile][0] && w <= kGridTileWidths[tile][1];
 }
 constexpr int kMaxWidth = 8;    // largest lateral kernel width
+constexpr int kMaxFftLength = 4096;  // longest lateral transform (oversampled grid side)
+// back-projection refuses plans and scans above this many terms
+// (virtual samples x frequencies x voxels), about a second of one GPU
+constexpr double kMaxBackprojectionTerms = 1.0e12;
 
 // Geometry of one virtual-sample record in the sorted list consumed by the
 // gridding kernel: source row of the echo, cell of the last tap, residual
@@ -75,6 +80,9 @@ struct Plan {
   // depth slabs: one sub-plan per slab, each with its own reference depth
   // (empty for a single-depth plan)
   std::vector<std::unique_ptr<Plan>> slabs;
+  // work that still reads this plan: queued or running server requests and
+  // batches built from it (sar_plan_destroy refuses while nonzero)
+  std::atomic<int> users{0};
   // timing
   bool timing = false;
   std::vector<hipEvent_t> events;  // kNumStages + 1 per recorded call

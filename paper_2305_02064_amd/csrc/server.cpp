@@ -150,6 +150,7 @@ void finish_locked(ServerState& s, Unit* u, sar_status st, const std::string& er
     r->t_done = now;
     r->done = true;
     s.arena.release(r->off, r->total);
+    r->plan->p.users.fetch_sub(1);
   }
   s.inflight -= (int)u->reqs.size();
   s.load[u->stream] -= 1;
@@ -351,6 +352,7 @@ sar_status sar_submit(sar_server server, sar_plan plan, const double* pos_xyz, i
       return fail(SAR_ERR_BUSY, "server is shutting down");
     }
     r->ticket = s.next_ticket++;
+    plan->p.users.fetch_add(1);  // released when the request finishes
     s.reqs[r->ticket] = r;
     s.queue.push_back(r);
     *ticket = r->ticket;

@@ -32,6 +32,7 @@ SAR_ECHO_C64 = 0
 SAR_ECHO_F16X2 = 1
 SAR_NO_COMPENSATION = 0x1
 SAR_FP32_ARGS = 0x2
+SAR_STOLT_DCF = 0x4
 SAR_BATCH_NO_GRAPH = 0x1
 
 STAGES = ("geometry+sort", "gridding", "fft_x", "fft_y", "stolt", "ifft_y", "ifft_x")
@@ -71,6 +72,10 @@ class sar_plan_info(ctypes.Structure):
         ("grid_tile", ctypes.c_int32), ("grid_tile_x", ctypes.c_int32), ("grid_tile_y", ctypes.c_int32),
         ("grid_freqs_per_lane", ctypes.c_int32),
         ("n_slabs", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("n_freq", ctypes.c_int32), ("echo_type", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("max_pos", ctypes.c_int64),
+        ("sigma_x", ctypes.c_double), ("sigma_y", ctypes.c_double),
     ]
 
 
@@ -154,6 +159,48 @@ def _dptr(t, name, dtype=None, shape=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _info(plan):
+    info = sar_plan_info()
+    _check(library().sar_plan_get_info(plan, ctypes.byref(info)))
+    return info
+
+
+def _check_scan(info, pos, n_pos, echo):
+    """Shapes and types of one scan's inputs against the plan, before any
+    pointer reaches the library (which cannot check buffer sizes itself)."""
+    n_pos = int(n_pos)
+    if not isinstance(pos, torch.Tensor) or not isinstance(echo, torch.Tensor):
+        raise TypeError("pos and echo must be torch tensors")
+    if pos.dtype != torch.float64 or tuple(pos.shape) != (n_pos, 3):
+        raise ValueError(f"pos must be float64 of shape ({n_pos}, 3), got {pos.dtype} {tuple(pos.shape)}")
+    n_val = n_pos * info.n_pair * info.n_freq
+    if info.echo_type == SAR_ECHO_C64:
+        ok = (echo.dtype == torch.complex64 and echo.numel() == n_val) or \
+             (echo.dtype == torch.float32 and echo.numel() == 2 * n_val)
+        want = f"complex64 with {n_val} values (or float32 with {2 * n_val})"
+    else:
+        ok = echo.dtype == torch.float16 and echo.numel() == 2 * n_val
+        want = f"float16 with {2 * n_val} values (real/imaginary pairs)"
+    if not ok:
+        raise ValueError(f"echo must be {want} for this plan ({n_pos} shots x {info.n_pair} pairs x "
+                         f"{info.n_freq} frequencies), got {echo.dtype} with {echo.numel()}")
+
+
+def _image_shape(info):
+    return (info.nx, info.ny, info.nz)
+
+
+def _spectrum_shape(info):
+    return (info.ny, info.nx, info.n_freq)
+
+
+def _check_workspace(plan, n_pos, workspace):
+    need = sar_plan_workspace_bytes(plan, n_pos)
+    if workspace.numel() * workspace.element_size() < need:
+        raise ValueError(f"workspace holds {workspace.numel() * workspace.element_size()} bytes; "
+                         f"the scan needs {need}")
+
+
 def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -196,21 +243,29 @@ def sar_plan_get_info(plan):
 
 
 def sar_reconstruct(plan, pos, n_pos, echo, echo_scale, image, workspace, stream=None):
-    _check(library().sar_reconstruct(plan, _dptr(pos, "pos", torch.float64), int(n_pos), _dptr(echo, "echo"),
-                                     float(echo_scale), _dptr(image, "image", torch.complex64),
-                                     _dptr(workspace, "workspace"), _stream(stream)))
+    info = _info(plan)
+    _check_scan(info, pos, n_pos, echo)
+    args = (_dptr(pos, "pos", torch.float64), int(n_pos), _dptr(echo, "echo"), float(echo_scale),
+            _dptr(image, "image", torch.complex64, _image_shape(info)), _dptr(workspace, "workspace"))
+    _check_workspace(plan, n_pos, workspace)
+    _check(library().sar_reconstruct(plan, *args, _stream(stream)))
 
 
 def sar_spectrum(plan, pos, n_pos, echo, echo_scale, spectrum, workspace, stream=None):
-    _check(library().sar_spectrum(plan, _dptr(pos, "pos", torch.float64), int(n_pos), _dptr(echo, "echo"),
-                                  float(echo_scale), _dptr(spectrum, "spectrum", torch.complex64),
-                                  _dptr(workspace, "workspace"), _stream(stream)))
+    info = _info(plan)
+    _check_scan(info, pos, n_pos, echo)
+    args = (_dptr(pos, "pos", torch.float64), int(n_pos), _dptr(echo, "echo"), float(echo_scale),
+            _dptr(spectrum, "spectrum", torch.complex64, _spectrum_shape(info)), _dptr(workspace, "workspace"))
+    _check_workspace(plan, n_pos, workspace)
+    _check(library().sar_spectrum(plan, *args, _stream(stream)))
 
 
 def sar_image_from_spectrum(plan, spectrum, image, workspace, stream=None):
-    _check(library().sar_image_from_spectrum(plan, _dptr(spectrum, "spectrum", torch.complex64),
-                                             _dptr(image, "image", torch.complex64),
-                                             _dptr(workspace, "workspace"), _stream(stream)))
+    info = _info(plan)
+    args = (_dptr(spectrum, "spectrum", torch.complex64, _spectrum_shape(info)),
+            _dptr(image, "image", torch.complex64, _image_shape(info)), _dptr(workspace, "workspace"))
+    _check_workspace(plan, 0, workspace)
+    _check(library().sar_image_from_spectrum(plan, *args, _stream(stream)))
 
 
 def sar_plan_set_timing(plan, enable):
@@ -246,6 +301,9 @@ def sar_submit(server, plan, pos, n_pos, echo, echo_scale, image):
     """Queue one scan; pos and echo are both device tensors or both host tensors."""
     if pos.is_cuda != echo.is_cuda:
         raise ValueError("pos and echo must both be on the device or both on the host")
+    info = _info(plan)
+    _check_scan(info, pos, n_pos, echo)
+    _dptr(image, "image", torch.complex64, _image_shape(info))
     t = ctypes.c_uint64()
     _check(library().sar_submit(server, plan, _ptr(pos, "pos", torch.float64), int(n_pos), _ptr(echo, "echo"),
                                 1 if echo.is_cuda else 0, float(echo_scale),
@@ -290,6 +348,14 @@ class Batch:
         if len(pos) != n or len(echo) != n:
             raise ValueError(f"need {n} position and echo tensors")
         images = [p.new_image() for p in self.plans] if images is None else images
+        if len(images) != n:
+            raise ValueError(f"need {n} images")
+        for p, ps, e, im in zip(self.plans, pos, echo, images):
+            info = _info(p.handle)
+            _check_scan(info, ps, ps.shape[0], e)
+            _dptr(ps, "pos", torch.float64)
+            _dptr(e, "echo")
+            _dptr(im, "image", torch.complex64, _image_shape(info))
         vp = ctypes.c_void_p
         P = (vp * n)(*[_dptr(t, "pos", torch.float64).value for t in pos])
         N = (ctypes.c_int64 * n)(*[t.shape[0] for t in pos])
@@ -325,7 +391,9 @@ class Server:
     def submit(self, plan, pos, echo, image=None, echo_scale=1.0):
         image = plan.new_image() if image is None else image
         ticket = sar_submit(self.handle, plan.handle, pos, pos.shape[0], echo, echo_scale, image)
-        self._held[ticket] = (pos, echo, image)
+        # the plan too must outlive the request: keep the Plan object (whose
+        # finaliser destroys the handle) referenced until the scan is collected
+        self._held[ticket] = (pos, echo, image, plan)
         return ticket
 
     def poll(self, ticket):
@@ -411,10 +479,15 @@ class Plan:
     def backproject(self, pos, echo, image=None, echo_scale=1.0, stream=None):
         """Direct back-projection on the plan's grid (sar_backproject)."""
         image = self.new_image() if image is None else image
+        _check_scan(self.info_struct(), pos, pos.shape[0], echo)
         _check(library().sar_backproject(self.handle, _dptr(pos, "pos", torch.float64), int(pos.shape[0]),
                                          _dptr(echo, "echo"), float(echo_scale),
-                                         _dptr(image, "image", torch.complex64), _stream(stream)))
+                                         _dptr(image, "image", torch.complex64, _image_shape(self.info_struct())),
+                                         _stream(stream)))
         return image
+
+    def info_struct(self):
+        return _info(self.handle)
 
     def set_grid_tile(self, tile):
         _check(library().sar_plan_set_grid_tile(self.handle, int(tile)))
@@ -424,6 +497,7 @@ class Plan:
         """Time the gridding tile configurations on this scan and keep the
         fastest (sar_plan_autotune); returns the chosen configuration."""
         t = ctypes.c_int32()
+        _check_scan(self.info_struct(), pos, pos.shape[0], echo)
         _check(library().sar_plan_autotune(self.handle, _dptr(pos, "pos", torch.float64), int(pos.shape[0]),
                                            _dptr(echo, "echo"), float(echo_scale), _dptr(self.ws, "workspace"),
                                            _stream(stream), ctypes.byref(t)))

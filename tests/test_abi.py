@@ -132,3 +132,72 @@ def test_grid_tile_arguments():
     assert lib.sar_plan_set_grid_tile(None, 0) == sar.SAR_ERR_INVALID
     t = ctypes.c_int32()
     assert lib.sar_plan_autotune(None, None, 0, None, 1.0, None, None, ctypes.byref(t)) == sar.SAR_ERR_INVALID
+
+
+def test_oversampled_grid_beyond_longest_transform_is_refused_at_plan_creation():
+    # 2048 voxels at upsample 3 asks for 6144+ cells along x: refused before any
+    # kernel is queued (the lateral transforms stop at 4096 points)
+    sar = _sar()
+    with pytest.raises(sar.SarError) as ei:
+        sar.sar_plan_create(**_desc_kwargs(nx=2048, upsample=3.0))
+    assert ei.value.status == sar.SAR_ERR_UNSUPPORTED
+    assert "4096" in str(ei.value)
+
+
+def _fake_info(sar, **over):
+    info = sar.sar_plan_info()
+    vals = dict(nx=8, ny=16, nz=4, n_freq=5, n_pair=2, echo_type=sar.SAR_ECHO_C64, max_pos=10)
+    vals.update(over)
+    for k, v in vals.items():
+        setattr(info, k, v)
+    return info
+
+
+@pytest.mark.parametrize("case", ["pos_flat", "pos_rows", "pos_dtype", "echo_size", "echo_dtype",
+                                  "half_as_c64", "c64_as_half"])
+def test_wrappers_check_scan_inputs_against_the_plan(case):
+    # the C ABI receives raw pointers and cannot check buffer sizes: the Python
+    # binding compares every scan input with the plan before any pointer is
+    # passed on (CPU tensors here; the check runs before the device check)
+    import torch
+    sar = _sar()
+    n = 3
+    pos = torch.zeros((n, 3), dtype=torch.float64)
+    echo = torch.zeros((n, 2, 5), dtype=torch.complex64)
+    info = _fake_info(sar)
+    if case == "pos_flat":
+        pos = pos.reshape(-1)
+    elif case == "pos_rows":
+        pos = torch.zeros((n + 1, 3), dtype=torch.float64)
+    elif case == "pos_dtype":
+        pos = pos.float()
+    elif case == "echo_size":
+        echo = torch.zeros((n, 2, 4), dtype=torch.complex64)
+    elif case == "echo_dtype":
+        echo = echo.to(torch.complex128)
+    elif case == "half_as_c64":
+        echo = torch.zeros((n, 2, 5, 2), dtype=torch.float16)
+    elif case == "c64_as_half":
+        info = _fake_info(sar, echo_type=sar.SAR_ECHO_F16X2)
+    with pytest.raises(ValueError):
+        sar._check_scan(info, pos, n, echo)
+
+
+def test_wrappers_accept_matching_inputs_and_check_outputs(monkeypatch):
+    import torch
+    sar = _sar()
+    info = _fake_info(sar)
+    sar._check_scan(info, torch.zeros((3, 3), dtype=torch.float64), 3, torch.zeros((3, 2, 5), dtype=torch.complex64))
+    sar._check_scan(info, torch.zeros((3, 3), dtype=torch.float64), 3, torch.zeros((3, 2, 5, 2), dtype=torch.float32))
+    h = _fake_info(sar, echo_type=sar.SAR_ECHO_F16X2)
+    sar._check_scan(h, torch.zeros((3, 3), dtype=torch.float64), 3, torch.zeros((3, 2, 5, 2), dtype=torch.float16))
+    assert sar._image_shape(info) == (8, 16, 4) and sar._spectrum_shape(info) == (16, 8, 5)
+    # a wrong image shape is caught before the library call
+    calls = []
+    monkeypatch.setattr(sar, "_info", lambda plan: info)
+    monkeypatch.setattr(sar, "library", lambda: calls.append(1))
+    with pytest.raises(ValueError):
+        sar.sar_reconstruct(None, torch.zeros((3, 3), dtype=torch.float64), 3,
+                            torch.zeros((3, 2, 5), dtype=torch.complex64), 1.0,
+                            torch.zeros((8, 16, 5), dtype=torch.complex64), torch.zeros(16, dtype=torch.uint8))
+    assert not calls

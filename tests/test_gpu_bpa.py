@@ -67,3 +67,19 @@ def test_fast_method_peaks_match_backprojection(torch_cuda):
     gr = np.array(np.unravel_index(np.argmax(np.abs(o_r)), o_r.shape))
     print(f"peak: back-projection {gb}, fast method {gr}")
     assert np.abs(gb - gr).max() <= 1
+
+
+def test_backprojection_cost_limit(torch_cuda):
+    # 512 shots x 8 pairs x 256 frequencies onto 256 x 256 x 256 voxels is
+    # 1.8e13 terms: refused up front instead of one dispatch of many seconds
+    from paper_2305_02064_amd import sar
+    tx, rx = awr1443_layout()
+    grid = ImageGrid(nx=256, ny=256, nz=256, x0=-0.1, y0=-0.1, z0=0.2, dx=1e-3, dy=1e-3, dz=1e-3,
+                     z_ref=0.0, z_focus=0.3)
+    plan = sar.Plan(tx, rx, sweep(256), grid, 512, workspace=False)
+    pos = torch_cuda.zeros((512, 3), dtype=torch_cuda.float64, device="cuda")
+    echo = torch_cuda.zeros((512, 8, 256), dtype=torch_cuda.complex64, device="cuda")
+    with pytest.raises(sar.SarError) as ei:
+        plan.backproject(pos, echo)
+    assert ei.value.status == sar.SAR_ERR_UNSUPPORTED
+    assert "1e12" in str(ei.value)

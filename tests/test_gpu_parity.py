@@ -206,6 +206,25 @@ def test_no_compensation_flag(torch_cuda, tiny):
     assert err <= IMAGE_TOL
 
 
+@pytest.mark.parametrize("nz", [16, 1])
+def test_stolt_jacobian_flag(torch_cuda, tiny, nz):
+    # SAR_STOLT_DCF: filter factor k_z times dk_z/dk = 4k/k_z, in the oracle
+    # (rma_filter(dcf=True)) and in the Stolt kernel (3-D) and the plane sum (nz = 1)
+    from paper_2305_02064_amd import sar
+    scan, _, _ = tiny
+    g = scan.grid if nz > 1 else _plane_grid(scan.grid, 0.3)
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, g, dcf=True)
+    plan = sar.Plan(scan.tx_xy, scan.rx_xy, scan.freq, g, scan.n_pos, flags=sar.SAR_STOLT_DCF)
+    pos, echo, _ = to_device(scan)
+    img = plan.reconstruct(pos, echo).cpu().numpy()
+    err = rel_l2(img, ref)
+    print(f"Stolt Jacobian image (nz {nz}) rel-L2 {err:.3e}")
+    assert err <= IMAGE_TOL
+    assert peak_ok(img, ref)
+    plain = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, g)
+    assert rel_l2(plain, ref) > 0.05   # the flag changes the image
+
+
 def test_empty_scan_gives_zero_image(torch_cuda, tiny):
     scan, _, _ = tiny
     plan = make_plan(scan)

@@ -200,3 +200,54 @@ def test_destroy_waits_for_pending_scans(torch_cuda, mix):
     srv.close()
     for i, img in enumerate(imgs):
         assert rel_l2(img.cpu().numpy(), refs[i].cpu().numpy()) <= SAME_TOL
+
+
+def test_plan_dropped_after_submit_stays_alive(torch_cuda, mix):
+    # the binding keeps the Plan object of a queued request referenced, so a
+    # caller that drops its plan right after submitting still gets its image
+    import gc
+    from paper_2305_02064_amd import sar
+    scans, refs = mix
+    sc, plan, pos, echo = scans[1]
+    srv = sar.Server(2 << 30)
+    try:
+        tmp = sar.Plan(sc.tx_xy, sc.rx_xy, sc.freq, sc.grid, sc.n_pos, workspace=False)
+        t = srv.submit(tmp, pos, echo)
+        del tmp
+        gc.collect()
+        _, img = srv.wait(t)
+    finally:
+        srv.close()
+    assert rel_l2(img.cpu().numpy(), refs[1].cpu().numpy()) <= SAME_TOL
+
+
+def test_plan_destroy_is_busy_while_used(torch_cuda, mix):
+    # sar_plan_destroy refuses a plan with an unfinished server request or a
+    # live batch, and succeeds once they are gone
+    from paper_2305_02064_amd import sar
+    scans, _ = mix
+    sc, _, pos, echo = scans[0]
+    h = sar.sar_plan_create(sc.tx_xy, sc.rx_xy, sc.freq, sc.grid.nx, sc.grid.ny, sc.grid.nz, sc.grid.x0,
+                            sc.grid.y0, sc.grid.z0, sc.grid.dx, sc.grid.dy, sc.grid.dz, sc.grid.z_ref,
+                            sc.grid.z_focus, sc.n_pos)
+    srv = sar.Server(64 << 20)   # about one scan at a time: requests wait in the queue
+    img = torch_cuda.empty((sc.grid.nx, sc.grid.ny, sc.grid.nz), dtype=torch_cuda.complex64, device="cuda")
+    try:
+        tickets = [sar.sar_submit(srv.handle, h, pos, sc.n_pos, echo, 1.0, img) for _ in range(4)]
+        with pytest.raises(sar.SarError) as ei:
+            sar.sar_plan_destroy(h)
+        assert ei.value.status == sar.SAR_ERR_BUSY
+        for t in tickets:
+            while not sar.sar_poll(srv.handle, t)[0]:
+                pass
+    finally:
+        srv.close()
+    # a batch holds its plans too
+    wrapper = type("P", (), {})()
+    wrapper.handle, wrapper.device = h, torch_cuda.device("cuda", 0)
+    b = sar.Batch([wrapper], graph=False)
+    with pytest.raises(sar.SarError) as ei:
+        sar.sar_plan_destroy(h)
+    assert ei.value.status == sar.SAR_ERR_BUSY
+    b.close()
+    sar.sar_plan_destroy(h)

@@ -251,6 +251,32 @@ def test_stolt_sum_uniform_kz_is_inverse_fft():
     assert _rel(z, n * np.fft.ifft(f, axis=-1)) < 1e-12
 
 
+def test_stolt_jacobian_option_turns_the_sum_into_an_integral_over_kz():
+    # With the optional Jacobian dk_z/dk = 4k/k_z (differentiating Eq. (14) at
+    # fixed lateral wavenumber) a trapezoid-weighted sum over the frequency
+    # samples of one column, sum_i w_i (dk_z/dk)_i exp(j k_z,i z), is the
+    # integral over k_z of exp(j k_z z), whose closed form is
+    # (exp(j k_z,hi z) - exp(j k_z,lo z)) / (j z).  The spectrum 1/k_z cancels
+    # the filter's own k_z factor of Eq. (15).  Without the option (or with a
+    # wrong factor) the sum is an integral over k instead and misses by about
+    # the Jacobian, about 2.35 to 2.39 along this column.
+    k = oracle.wavenumber(np.linspace(77e9, 81e9, 8001))
+    dk = k[1] - k[0]
+    kx, ky = np.array([1.1 * k[0]]), np.array([0.0])
+    kz, mask = oracle.axial_wavenumber(k, kx, ky)
+    assert mask.all()
+    w = np.full(len(k), dk)
+    w[0] = w[-1] = 0.5 * dk
+    spec = (w / kz[0, 0])[None, None, :]
+    z = np.array([0.05, 0.13, 0.3])
+    lo, hi = kz[0, 0, 0], kz[0, 0, -1]
+    ref = (np.exp(1j * hi * z) - np.exp(1j * lo * z)) / (1j * z)
+    got = oracle.stolt_direct(oracle.rma_filter(spec, kz, mask, 0.0, k, dcf=True), kz, mask, z)[0, 0]
+    assert _rel(got, ref) < 1e-4
+    plain = oracle.stolt_direct(oracle.rma_filter(spec, kz, mask, 0.0), kz, mask, z)[0, 0]
+    assert _rel(plain, ref) > 0.3
+
+
 def test_idft2_bruteforce():
     rng = np.random.default_rng(12)
     nx, ny, nz = 6, 4, 2
