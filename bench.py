@@ -478,6 +478,31 @@ def comparison_tiny(reps=20):
     return out
 
 
+def clustered_bench(plan, pos, echo, image, stream, reps=10):
+    """The large scan with its middle quarter of shots (32 768) moved to one
+    position: eight cells of the gridding grid then hold 32 768 samples each.
+    Same echo values (the kernels' work does not depend on them); per-stage
+    milliseconds, mean of reps calls."""
+    import torch
+    from paper_2305_02064_amd import sar
+    n = pos.shape[0]
+    p2 = pos.clone()
+    q0 = 3 * n // 8
+    p2[q0:q0 + n // 4] = pos[n // 2]
+    plan.reconstruct(p2, echo, image)
+    torch.cuda.synchronize()
+    sar.sar_plan_set_timing(plan.handle, True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.reconstruct(p2, echo, image)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    stage_ms, n_calls = sar.sar_plan_stage_times(plan.handle)
+    sar.sar_plan_set_timing(plan.handle, False)
+    return {"workload": f"large scan, shots {q0}..{q0 + n // 4 - 1} at one position", "ms_per_scan": ms,
+            "stage_ms": {k: v / max(n_calls, 1) for k, v in stage_ms.items()}}
+
+
 def copy_calibration(nbytes, launches=3):
     import torch
     x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -505,6 +530,8 @@ def main():
                     help="Poisson rates for a sweep with every request's inputs in pinned host memory (opt-in)")
     ap.add_argument("--oracle-uneven", action="store_true",
                     help="also time the FP64 oracle beside the GPU on 12 scans of the uneven batch (minutes of CPU)")
+    ap.add_argument("--clustered", action="store_true",
+                    help="also time the large scan with a quarter of its shots at one position (a dwelling hand)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the library forms each image on a single device (got --gpus {args.gpus})",
@@ -618,6 +645,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(scan, echo_host)
     if args.oracle_uneven:
         out["oracle_uneven"] = oracle_uneven()
+    if args.clustered:
+        out["clustered"] = clustered_bench(plan, pos, echo, image, stream)
     print(json.dumps(out))
     plan.close()
 

@@ -92,7 +92,8 @@ typedef enum { SAR_ECHO_C64 = 0, SAR_ECHO_F16X2 = 1 } sar_echo_type;
  * Constraints (SAR_ERR_INVALID otherwise):
  *   n_tx, n_rx >= 1, n_tx * n_rx <= 4096; n_freq >= 1, freq_hz finite,
  *   strictly increasing, > 0;
- *   nx, ny powers of two in [8, 2048]; nz 1 or a power of two in [2, 512]
+ *   nx, ny in [8, 2048], each a product 2^a 3^b 5^c (odd sides included);
+ *   nz 1 or a power of two in [2, 512]
  *   (nz = 1: one x-y plane at z0, the paper's 2-D image at a known depth,
  *   Sec. V-A; steps a4-a5 become one exact sum over frequency per column);
  *   dx, dy, dz > 0; the scene reference depth and the image volume in front
@@ -101,8 +102,11 @@ typedef enum { SAR_ECHO_C64 = 0, SAR_ECHO_F16X2 = 1 } sar_echo_type;
  *   tol 0 or in (0, 0.1]: target relative L2 error of the lateral NUFFT
  *   (0 selects 1e-3); the kernel width is the smallest whose calibrated
  *   error 5 exp(-pi W sqrt(1 - 1/sigma)) meets it;
- *   upsample 0 (automatic = 2) or in [2, 4] (the lateral grid is the next power
- *   of two at or above upsample * n; SAR_ERR_UNSUPPORTED otherwise);
+ *   upsample 0 (automatic: 2, or what sar_plan_autotune stored for the plan's
+ *   size bucket, see below) or in [1.25, 4] (SAR_ERR_UNSUPPORTED otherwise):
+ *   the lateral grid has the smallest multiple of 8 cells of the form
+ *   2^a 3^b 5^c at or above upsample * n along each axis, at most 4096
+ *   (SAR_ERR_UNSUPPORTED beyond; sar_plan_info reports the effective ratio);
  *   kernel_width 0 (from tol) or 3..8 taps;
  *   n_slabs 0 or 1 (one reference depth z_focus for the whole volume) or a
  *   power of two that divides nz: depth slabs, see below.
@@ -220,17 +224,29 @@ sar_status sar_image_from_spectrum(sar_plan plan, const void* d_spectrum, void* 
 sar_status sar_backproject(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo, float echo_scale,
                            void* d_image, sar_stream_t stream);
 
-/* Autotuner: times every gridding tile configuration compiled for the plan's
- * kernel width on the given scan, which should be representative of the
- * plan's workload, and keeps the fastest for every later call of this plan:
+/* Autotuner: times the whole pipeline on the given scan (which should be
+ * representative of the plan's workload) for every candidate and keeps the
+ * fastest for every later call of this plan.  Candidates: the lateral
+ * oversampling (1.25, 1.5 and 2 when the plan was created with upsample = 0,
+ * else only the requested one; the kernel width follows the plan's tolerance
+ * at each) times every gridding tile configuration compiled for that width:
  *   0: 4 x 4 cells, 2 frequencies per lane (kernels of 3 to 8 taps);
  *   1: 8 x 8 cells, 1 frequency per lane (3 to 5 taps);
  *   2: 8 x 4 cells, 2 frequencies per lane (5 and 6 taps).
- * Runs a0-a2 a few times on `stream` and waits for them (synchronous).  The
- * default before tuning: tile 1 when the sweep has at most 64 frequencies
- * (and the width allows it), else tile 0.  Tune before creating
- * batches from the plan and not while other calls use it.  tile_out (may be
- * NULL) receives the chosen configuration.  Arguments as sar_reconstruct. */
+ * Candidates whose workspace would exceed the plan's current
+ * sar_plan_workspace_bytes(plan, n_pos) are skipped, so d_workspace as sized
+ * before the call stays large enough.  Runs each candidate a few times on
+ * `stream` and waits for them (synchronous).  The default before tuning:
+ * oversampling 2, tile 1 when the sweep has at most 64 frequencies (and the
+ * width allows it), else tile 0.  If the environment variable
+ * SAR_AUTOTUNE_FILE names a file, the choice is also stored there for the
+ * plan's size bucket (image and sweep sizes, pairs, echo type, flags,
+ * tolerance, n_pos rounded up to a power of two), and plans created later
+ * with upsample = 0 and a max_pos in the same bucket start from it.
+ * SAR_ERR_BUSY while batches or server requests use the plan; tune before
+ * creating batches from it and not while other calls use it.  tile_out (may
+ * be NULL) receives the chosen tile; sar_plan_get_info reports the rest.
+ * Arguments as sar_reconstruct. */
 sar_status sar_plan_autotune(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,
                              float echo_scale, void* d_workspace, sar_stream_t stream, int32_t* tile_out);
 

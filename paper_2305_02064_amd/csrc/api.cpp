@@ -1,9 +1,11 @@
 // C ABI entry points (include/sar.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "launch.hpp"
 #include "sar_internal.hpp"
@@ -132,9 +134,10 @@ sar_status run_back(const Plan& p, const float2* spec, void* d_image, const Work
   gy.s_out_o = 0;
   gy.s_out_k = (int64_t)p.nx * p.nz;
   gy.n_out = p.ny;
-  gy.centred = 0;
+  gy.centred = (p.ny & 1) ? 2 : 0;  // odd: shifted output with a phase factor
   gy.sign = +1;
   gy.scale = p.d_signy;
+  gy.cscale = p.d_posty;
   gy.tw = p.d_tw_ny;
   if ((st = launch_fft_lines(gy, sink)) != SAR_OK) return st;
   if (tm) tm->mark(first_mark + 2);
@@ -149,9 +152,10 @@ sar_status run_back(const Plan& p, const float2* spec, void* d_image, const Work
   gx.s_out_o = p.out_nz;
   gx.s_out_k = (int64_t)p.ny * p.out_nz;
   gx.n_out = p.nx;
-  gx.centred = 0;
+  gx.centred = (p.nx & 1) ? 2 : 0;
   gx.sign = +1;
   gx.scale = p.d_signx;
+  gx.cscale = p.d_postx;
   gx.tw = p.d_tw_nx;
   gx.nt_out = 1;  // the image: not read again by this library
   if ((st = launch_fft_lines(gx, sink)) != SAR_OK) return st;
@@ -306,43 +310,72 @@ sar_status sar_plan_autotune(sar_plan plan, const double* d_pos, int64_t n_pos, 
   sar_status st = check_call(plan, n_pos, d_pos, d_echo, d_workspace, d_workspace);
   if (st != SAR_OK) return st;
   Plan& p = plan->p;
+  if (p.users.load() > 0) return fail(SAR_ERR_BUSY, "plan is used by a batch or by server requests");
   DeviceGuard g(p.device);
   hipStream_t s = (hipStream_t)stream;
-  Workspace ws;
-  workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
-  DirectSink sink(s);
-  if ((st = launch_geometry_sort(p, d_pos, n_pos, n_pos, ws, sink)) != SAR_OK) return st;
+  // every candidate must fit the workspace the caller sized for the plan as it is
+  const size_t ws_have = workspace_bytes(p, n_pos, nullptr, nullptr);
+  std::vector<Plan*> all{&p};
+  for (auto& sub : p.slabs) all.push_back(sub.get());
+  const double cur_up = std::min((double)p.mx / p.nx, (double)p.my / p.ny);
+  std::vector<double> sigmas;
+  if (p.up_req > 0)
+    sigmas.push_back(p.up_req);
+  else
+    sigmas = {kMinUpsample, 1.5, 2.0};
+  auto adopt = [&](double up, int tile) -> sar_status {
+    for (Plan* q : all) {
+      sar_status s2 = choose_lateral(*q, up);
+      if (s2 == SAR_OK) s2 = upload_lateral(*q);
+      if (s2 != SAR_OK) return s2;
+      if (tile >= 0) q->grid_tile = tile;
+    }
+    return SAR_OK;
+  };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if ((st = check_hip(hipEventCreate(&e0), "event create")) != SAR_OK) return st;
   if ((st = check_hip(hipEventCreate(&e1), "event create")) != SAR_OK) {
     (void)hipEventDestroy(e0);
     return st;
   }
-  const int old_tile = p.grid_tile;
-  int best = old_tile;
+  double best_up = cur_up;
+  int best_tile = p.grid_tile;
   float best_ms = 0.f;
-  for (int t = 0; t < kNumGridTiles && st == SAR_OK; ++t) {
-    if (!grid_tile_compiled(t, p.w)) continue;
-    p.grid_tile = t;
-    float t_min = 0.f;
-    for (int rep = 0; rep < 4 && st == SAR_OK; ++rep) {  // first run warms up
-      st = check_hip(hipEventRecord(e0, s), "event record");
-      if (st == SAR_OK) st = launch_gridding(p, d_echo, echo_scale, ws, ws.region_a, sink);
-      if (st == SAR_OK) st = check_hip(hipEventRecord(e1, s), "event record");
-      if (st == SAR_OK) st = check_hip(hipEventSynchronize(e1), "event wait");
-      float ms = 0.f;
-      if (st == SAR_OK) st = check_hip(hipEventElapsedTime(&ms, e0, e1), "event time");
-      if (st == SAR_OK && rep > 0 && (rep == 1 || ms < t_min)) t_min = ms;
+  DirectSink sink(s);
+  for (double up : sigmas) {
+    if (adopt(up, -1) != SAR_OK) continue;  // e.g. a grid beyond the longest transform
+    if (workspace_bytes(p, n_pos, nullptr, nullptr) > ws_have) continue;
+    for (int t = 0; t < kNumGridTiles && st == SAR_OK; ++t) {
+      if (!grid_tile_compiled(t, p.w)) continue;
+      for (Plan* q : all) q->grid_tile = t;
+      // the whole pipeline, its image written into the workspace's second
+      // region (free once the last transform runs); first run warms up
+      Workspace ws;
+      workspace_bytes(p, n_pos, &ws, (char*)d_workspace);
+      float t_min = 0.f;
+      for (int rep = 0; rep < 4 && st == SAR_OK; ++rep) {
+        st = check_hip(hipEventRecord(e0, s), "event record");
+        if (st == SAR_OK)
+          st = describe_reconstruct(p, d_pos, n_pos, n_pos, d_echo, echo_scale, ws.region_b, d_workspace, sink);
+        if (st == SAR_OK) st = check_hip(hipEventRecord(e1, s), "event record");
+        if (st == SAR_OK) st = check_hip(hipEventSynchronize(e1), "event wait");
+        float ms = 0.f;
+        if (st == SAR_OK) st = check_hip(hipEventElapsedTime(&ms, e0, e1), "event time");
+        if (st == SAR_OK && rep > 0 && (rep == 1 || ms < t_min)) t_min = ms;
+      }
+      if (st == SAR_OK && (best_ms == 0.f || t_min < best_ms)) {
+        best_ms = t_min;
+        best_up = up;
+        best_tile = t;
+      }
     }
-    if (st == SAR_OK && (best_ms == 0.f || t_min < best_ms)) {
-      best_ms = t_min;
-      best = t;
-    }
+    if (st != SAR_OK) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  p.grid_tile = st == SAR_OK ? best : old_tile;
-  for (auto& sub : p.slabs) sub->grid_tile = p.grid_tile;
+  const sar_status st_adopt = adopt(best_up, best_tile);
+  if (st == SAR_OK) st = st_adopt;
+  if (st == SAR_OK) tuning_store(p, n_pos, best_up, best_tile);
   if (tile_out) *tile_out = p.grid_tile;
   return st;
 }

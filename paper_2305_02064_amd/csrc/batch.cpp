@@ -327,8 +327,9 @@ sar_status sar_batch_reconstruct(sar_batch batch, const double* const* d_pos, co
 sar_status sar_batch_destroy(sar_batch batch) {
   if (!batch) return SAR_OK;
   DeviceGuard g(batch->s.device);
+  const std::vector<sar_plan> plans = batch->s.plans;  // release() waits for the last call, then forgets them
   release(batch->s);
-  for (sar_plan q : batch->s.plans) q->p.users.fetch_sub(1);
+  for (sar_plan q : plans) q->p.users.fetch_sub(1);
   delete batch;
   return SAR_OK;
 }

@@ -90,7 +90,7 @@ __device__ __forceinline__ void FftBody<L1, L2, BC, SIGN>::run(const FftLines& a
         int P;
         if (a.centred) {
           const int h = a.n_out / 2;
-          P = k < h ? k + h : (k >= L - h ? k - L + h : -1);
+          P = k < a.n_out - h ? k + h : (k >= L - h ? k - L + h : -1);
         } else {
           P = k;
         }
@@ -107,6 +107,185 @@ __device__ __forceinline__ void FftBody<L1, L2, BC, SIGN>::run(const FftLines& a
   }
 }
 
+// ---------------------------------------------------------------------------
+// Any length 2^a 3^b 5^c (the non-power-of-two image sides and oversampled
+// grids): a block holds BC batch columns of the whole line in LDS and runs
+// self-sorting (Stockham) radix-8/4/2/3/5 passes between two LDS buffers.  Pass
+// p with radix R, after passes whose radices multiply to Ns, maps butterfly j
+// (k = j mod Ns) from x[j + q L/R] to y[(j / Ns) Ns R + k + q Ns] after the
+// twiddles w_{Ns R}^(q k) and an R-point DFT; the last pass leaves X in natural
+// order.  The epilogue is that of the power-of-two kernel plus the shifted,
+// complex-scaled placement of odd inverse lengths.
+constexpr int kMixMaxPasses = 16;
+constexpr int kMixThreads = 256;
+constexpr int kMixMaxElems = 8192;  // L x BC complex values per LDS buffer
+
+struct FftMixedArgs {
+  FftLines f;
+  int lbc;  // log2 of the batch columns per block
+  int npass;
+  int rad[kMixMaxPasses];
+  // n / d as umulhi(n, ceil(2^32 / d)), exact for n < 2^16, d <= 4096 (checked
+  // exhaustively): the pass's Ns (0 when Ns = 1) and the length
+  uint32_t mag_ns[kMixMaxPasses];
+  uint32_t mag_l;
+};
+
+// R-point DFT in natural order, X[m] = sum_n a[n] exp(SIGN j 2 pi n m / R)
+template <int R, int SIGN>
+__device__ __forceinline__ void small_dft(float2 (&a)[R]) {
+  if constexpr ((R & (R - 1)) == 0) {
+    reg_dft_dif<R, SIGN>(a);   // output in bit-reversed order
+    float2 t[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) t[m] = a[ct_bitrev(m, ct_log2(R))];
+#pragma unroll
+    for (int m = 0; m < R; ++m) a[m] = t[m];
+  } else {
+    float2 t[R];
+    static_for<0, R>([&](auto mc) __attribute__((always_inline)) {
+      constexpr int m = decltype(mc)::value;
+      float2 acc = a[0];
+      static_for<1, R>([&](auto nc) __attribute__((always_inline)) {
+        constexpr int n = decltype(nc)::value;
+        acc = cadd(acc, twiddle_mul<(m * n) % R, R, SIGN>(a[n]));
+      });
+      t[m] = acc;
+    });
+#pragma unroll
+    for (int m = 0; m < R; ++m) a[m] = t[m];
+  }
+}
+
+template <int R, int SIGN>
+__device__ __forceinline__ void stockham_pass(const float2* __restrict__ x, float2* __restrict__ y, int L, int lbc,
+                                              int Ns, uint32_t mag_ns, uint32_t mag_l,
+                                              const float2* __restrict__ tw) {
+  const int BC = 1 << lbc;
+  const int m = L / R;
+  const int tstep = L / (Ns * R);  // w_{Ns R} = tw[tstep]
+  for (int i = threadIdx.x; i < (m << lbc); i += kMixThreads) {
+    const int b = i & (BC - 1);
+    const int j = i >> lbc;
+    const int g = mag_ns ? (int)__umulhi((uint32_t)j, mag_ns) : j;  // j / Ns
+    const int k = j - g * Ns;
+    float2 v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = x[((j + q * m) << lbc) + b];
+    if (k != 0) {
+      const int e = tstep * k;
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        const int t = q * e;
+        v[q] = cmul(v[q], tw[t - L * (int)__umulhi((uint32_t)t, mag_l)]);  // (q e) mod L
+      }
+    }
+    small_dft<R, SIGN>(v);
+    const int base = g * Ns * R + k;
+#pragma unroll
+    for (int q = 0; q < R; ++q) y[((base + q * Ns) << lbc) + b] = v[q];
+  }
+}
+
+template <int SIGN>
+struct FftMixedBody {
+  using Args = FftMixedArgs;
+  static constexpr int kThreads = kMixThreads;
+  static __device__ __forceinline__ void run(const FftMixedArgs& m, uint32_t blk, uint32_t) {
+    extern __shared__ float2 lds[];
+    const FftLines& a = m.f;
+    const int L = a.L;
+    const int BC = 1 << m.lbc;
+    const int64_t nbc = (a.B + BC - 1) / BC;
+    const int64_t o = blk / nbc;
+    const int64_t bc = blk - o * nbc;
+    float2* x = lds;
+    float2* y = lds + L * BC;
+    const float2* __restrict__ in = a.in + o * a.s_in_o + bc * BC;
+    for (int i = threadIdx.x; i < L * BC; i += kMixThreads) {
+      const int b = i & (BC - 1);
+      const int l = i >> m.lbc;
+      x[i] = bc * BC + b < a.B ? load_stream(&in[(int64_t)l * a.s_in_l + b]) : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    int Ns = 1;
+    for (int p = 0; p < m.npass; ++p) {
+      const int R = m.rad[p];
+      const uint32_t mg = m.mag_ns[p];
+      if (R == 8)
+        stockham_pass<8, SIGN>(x, y, L, m.lbc, Ns, mg, m.mag_l, a.tw);
+      else if (R == 4)
+        stockham_pass<4, SIGN>(x, y, L, m.lbc, Ns, mg, m.mag_l, a.tw);
+      else if (R == 2)
+        stockham_pass<2, SIGN>(x, y, L, m.lbc, Ns, mg, m.mag_l, a.tw);
+      else if (R == 3)
+        stockham_pass<3, SIGN>(x, y, L, m.lbc, Ns, mg, m.mag_l, a.tw);
+      else
+        stockham_pass<5, SIGN>(x, y, L, m.lbc, Ns, mg, m.mag_l, a.tw);
+      __syncthreads();
+      float2* t = x;
+      x = y;
+      y = t;
+      Ns *= R;
+    }
+    float2* __restrict__ out = a.out + o * a.s_out_o + bc * BC;
+    const int h = a.n_out / 2;
+    for (int i = threadIdx.x; i < L * BC; i += kMixThreads) {
+      const int b = i & (BC - 1);
+      const int k = i >> m.lbc;
+      if (bc * BC + b >= a.B) continue;
+      int P;
+      if (a.centred == 1)
+        P = k < a.n_out - h ? k + h : (k >= L - h ? k - L + h : -1);
+      else if (a.centred == 2)
+        P = k + h < L ? k + h : k + h - L;
+      else
+        P = k;
+      if (P < 0) continue;
+      float2 v = x[i];
+      if (a.centred == 2)
+        v = cmul(v, a.cscale[P]);
+      else if (a.scale)
+        v = cscale(v, a.scale[P]);
+      float2* dst = &out[(int64_t)P * a.s_out_k + b];
+      if (a.nt_out)
+        store_stream(dst, v);
+      else
+        *dst = v;
+    }
+  }
+};
+
+sar_status launch_mixed(const FftLines& a, LaunchSink& sink) {
+  FftMixedArgs m{};
+  m.f = a;
+  int n = a.L;
+  for (int r : {8, 4, 2, 3, 5})
+    while (n % r == 0) {
+      if (m.npass == kMixMaxPasses) return fail(SAR_ERR_UNSUPPORTED, "FFT length has too many factors");
+      m.rad[m.npass++] = r;
+      n /= r;
+    }
+  if (n != 1) return fail(SAR_ERR_UNSUPPORTED, "FFT length not a product of 2, 3 and 5: " + std::to_string(a.L));
+  if (a.L > kMixMaxElems) return fail(SAR_ERR_UNSUPPORTED, "FFT length too long: " + std::to_string(a.L));
+  int bc = 1;
+  while (bc < 16 && 2 * bc * a.L <= kMixMaxElems && bc < a.B) bc *= 2;
+  while ((1 << m.lbc) < bc) ++m.lbc;
+  auto magic = [](int d) { return d <= 1 ? 0u : (uint32_t)(((1ull << 32) + (uint64_t)d - 1) / (uint64_t)d); };
+  int ns = 1;
+  for (int q = 0; q < m.npass; ++q) {
+    m.mag_ns[q] = magic(ns);
+    ns *= m.rad[q];
+  }
+  m.mag_l = magic(a.L);
+  const int64_t nblk = (a.B + bc - 1) / bc * a.n_outer;
+  if (nblk <= 0) return SAR_OK;
+  if (nblk > 0x7fffffffLL) return fail(SAR_ERR_UNSUPPORTED, "FFT batch too large");
+  const size_t lds = 2 * (size_t)a.L * bc * sizeof(float2);
+  if (a.sign < 0) return launch_body<FftMixedBody<-1>>(sink, (uint32_t)nblk, lds, m, "fft launch");
+  return launch_body<FftMixedBody<+1>>(sink, (uint32_t)nblk, lds, m, "fft launch");
+}
+
 template <int L1, int L2, int BC>
 sar_status launch_lb(const FftLines& a, LaunchSink& sink) {
   const size_t lds = (size_t)L1 * (L2 + 1) * BC * sizeof(float2);
@@ -120,7 +299,16 @@ sar_status launch_lb(const FftLines& a, LaunchSink& sink) {
 
 }  // namespace
 
+bool is_5smooth(int64_t v) {
+  if (v < 1) return false;
+  for (int r : {2, 3, 5})
+    while (v % r == 0) v /= r;
+  return v == 1;
+}
+
 sar_status launch_fft_lines(const FftLines& a, LaunchSink& sink) {
+  // shifted placement (odd lengths) only in the mixed-radix kernel
+  if (a.centred == 2 || (a.L & (a.L - 1)) != 0) return launch_mixed(a, sink);
   // batch columns per block chosen so one block's LDS stays near 64 KiB; where
   // L is not a square, L1 > L2 so that every thread of the block loads and
   // transforms in the first pass (the load-bound one)
@@ -135,7 +323,7 @@ sar_status launch_fft_lines(const FftLines& a, LaunchSink& sink) {
     case 1024: return launch_lb<32, 32, 8>(a, sink);
     case 2048: return launch_lb<64, 32, 4>(a, sink);
     case 4096: return launch_lb<64, 64, 2>(a, sink);
-    default: return fail(SAR_ERR_UNSUPPORTED, "FFT length not supported: " + std::to_string(a.L));
+    default: return launch_mixed(a, sink);
   }
 }
 

@@ -3,10 +3,12 @@
 // Every Tx/Rx pair of every shot becomes a virtual element at the pair's
 // midpoint projected onto the plane Z_0 (Eqs. (3)-(4)); its residual path
 // beta (Eqs. (7), (12)) is kept for the phase compensation applied in the
-// gridding kernel.  The elements are then counting-sorted by the oversampled
-// grid cell of their first kernel tap so that the gridding kernel can walk
-// every sample whose support touches a tile as a handful of contiguous runs.
-// Within a cell the order is by source index, so results are reproducible.
+// gridding kernel.  The elements are then sorted by the oversampled grid cell
+// of their first kernel tap (per-cell counts and their scan give each cell's
+// start; a stable radix sort gives the order) so that the gridding kernel can
+// walk every sample whose support touches a tile as a handful of contiguous
+// runs.  Within a cell the order is by source index, so results are
+// reproducible.
 
 #include "device_common.hpp"
 #include "launch.hpp"
@@ -106,13 +108,12 @@ struct ZeroBody {
   }
 };
 
-// per virtual sample: first-tap cell (the sort key) and its rank in the cell
+// per virtual sample: first-tap cell (the sort key), counted per cell
 template <int W>
 struct KeysBody {
   struct Args {
     GeoArgs g;
     int32_t* key;
-    int32_t* rank;
     int32_t* count;
   };
   static constexpr int kThreads = 256;
@@ -126,7 +127,7 @@ struct KeysBody {
     sample_cells(a.g, m, l, W, gx, cx, gy, cy);
     const int k = wrap(cy, a.g.my) * a.g.mx + wrap(cx, a.g.mx);
     a.key[n] = k;
-    a.rank[n] = atomicAdd(&a.count[k], 1);
+    atomicAdd(&a.count[k], 1);
   }
 };
 
@@ -246,42 +247,113 @@ struct ScanAddBody {
   }
 };
 
-struct ScatterBody {
+// ---- stable least-significant-digit radix sort of the samples by cell -----
+// Each pass orders (key, index) pairs by one DB-bit digit of the key and keeps
+// the order of equal digits, so after the last pass the samples are sorted by
+// cell and, within a cell, by source index: the same order on every run,
+// whatever the cell counts (a dwelling hand can put thousands of samples in
+// one cell).  A pass is a per-tile digit histogram, an exclusive scan of the
+// histograms in digit-major order (the scan kernels above) and a scatter that
+// ranks equal digits within its tile in index order.  Every thread loads its
+// 16 elements of the tile at once, so a tile's loads are all in flight together.
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;                          // elements per thread per tile
+constexpr int kSortTile = kSortThreads * kSortRounds;    // 4096 elements
+
+template <int DB>
+struct RadixHistBody {
+  static constexpr int NB = 1 << DB;
   struct Args {
-    int64_t n_v;
     const int32_t* key;
-    const int32_t* rank;
-    const int32_t* start;
-    int32_t* order;
+    int64_t n;
+    int shift;
+    int ntiles;     // histogram stride: hist[digit * ntiles + tile]
+    int32_t* hist;
   };
-  static constexpr int kThreads = 256;
+  static constexpr int kThreads = kSortThreads;
   static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
-    const int64_t n = (int64_t)b * kThreads + threadIdx.x;
-    if (n >= a.n_v) return;
-    a.order[a.start[a.key[n]] + a.rank[n]] = (int32_t)n;
+    __shared__ int cnt[NB];
+    int k[kSortRounds];
+    const int64_t base = (int64_t)b * kSortTile + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kSortRounds; ++j) {
+      const int64_t i = base + (int64_t)j * kSortThreads;
+      k[j] = i < a.n ? a.key[i] : -1;
+    }
+    for (int d = threadIdx.x; d < NB; d += kSortThreads) cnt[d] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kSortRounds; ++j)
+      if (k[j] >= 0) atomicAdd(&cnt[(k[j] >> a.shift) & (NB - 1)], 1);
+    __syncthreads();
+    for (int d = threadIdx.x; d < NB; d += kSortThreads) a.hist[(int64_t)d * a.ntiles + b] = cnt[d];
   }
 };
 
-// One thread per cell: order the cell's samples by source index.
-struct SortCellsBody {
+template <int DB>
+struct RadixScatterBody {
+  static constexpr int NB = 1 << DB;
   struct Args {
-    int64_t ncell;
-    const int32_t* start;
-    int32_t* order;
+    const int32_t* key_in;
+    const int32_t* val_in;  // null: the element's own index (first pass)
+    int32_t* key_out;       // null: keys not needed after this pass
+    int32_t* val_out;
+    int64_t n;
+    int shift;
+    int ntiles;
+    const int32_t* offs;    // exclusive scan of the histograms, digit-major
   };
-  static constexpr int kThreads = 256;
+  static constexpr int kThreads = kSortThreads;
   static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
-    const int64_t c = (int64_t)b * kThreads + threadIdx.x;
-    if (c >= a.ncell) return;
-    const int s0 = a.start[c], s1 = a.start[c + 1];
-    for (int i = s0 + 1; i < s1; ++i) {
-      const int v = a.order[i];
-      int j = i - 1;
-      while (j >= s0 && a.order[j] > v) {
-        a.order[j + 1] = a.order[j];
-        --j;
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ int base_d[NB];             // next output slot per digit
+    __shared__ int wcnt[kWaves][NB];       // per-wave digit counts of a round
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    int kk[kSortRounds], vv[kSortRounds];
+    const int64_t base = (int64_t)b * kSortTile + tid;
+#pragma unroll
+    for (int j = 0; j < kSortRounds; ++j) {
+      const int64_t i = base + (int64_t)j * kSortThreads;
+      const bool valid = i < a.n;
+      kk[j] = valid ? a.key_in[i] : -1;
+      vv[j] = valid ? (a.val_in ? a.val_in[i] : (int)i) : 0;
+    }
+    for (int d = tid; d < NB; d += kSortThreads) base_d[d] = a.offs[(int64_t)d * a.ntiles + b];
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;   // lanes below this one
+#pragma unroll
+    for (int j = 0; j < kSortRounds; ++j) {
+      for (int d = tid; d < NB; d += kSortThreads)
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) wcnt[w][d] = 0;
+      __syncthreads();
+      const bool valid = kk[j] >= 0;
+      const int d = (kk[j] >> a.shift) & (NB - 1);
+      // lanes of this wave holding the same digit: they agree on every digit bit
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < DB; ++bit) {
+        const bool set = (d >> bit) & 1;
+        const uint64_t m = __ballot(set);
+        peers &= set ? m : ~m;
       }
-      a.order[j + 1] = v;
+      const int rank_w = __popcll(peers & lt);
+      if (valid && rank_w == 0) wcnt[wave][d] = __popcll(peers);
+      __syncthreads();
+      if (valid) {
+        int pos = base_d[d] + rank_w;
+        for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+        if (a.key_out) a.key_out[pos] = kk[j];
+        a.val_out[pos] = vv[j];
+      }
+      __syncthreads();
+      for (int dd = tid; dd < NB; dd += kSortThreads) {
+        int add = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) add += wcnt[w][dd];
+        base_d[dd] += add;
+      }
     }
   }
 };
@@ -327,6 +399,19 @@ struct RecordsBody {
 
 uint32_t blocks_for(int64_t n, int threads) { return (uint32_t)((n + threads - 1) / threads); }
 
+// one radix pass: digit histograms per tile, their scan, the stable scatter
+template <int DB, typename Scan>
+sar_status radix_pass(LaunchSink& sink, const int32_t* kin, const int32_t* vin, int32_t* kout, int32_t* vout,
+                      int64_t n_v, int shift, int ntiles, int32_t* hist, Scan& scan) {
+  const char* what = "geometry/sort launch";
+  const int64_t nhist = (int64_t)(1 << DB) * ntiles;
+  sar_status st;
+  if ((st = launch_body<RadixHistBody<DB>>(sink, ntiles, 0, {kin, n_v, shift, ntiles, hist}, what)) != SAR_OK)
+    return st;
+  if ((st = scan(hist, nhist, hist + nhist + 1)) != SAR_OK) return st;
+  return launch_body<RadixScatterBody<DB>>(sink, ntiles, 0, {kin, vin, kout, vout, n_v, shift, ntiles, hist}, what);
+}
+
 template <int W>
 sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, int64_t n_pos_grid,
                            const Workspace& ws, LaunchSink& sink) {
@@ -363,20 +448,40 @@ sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, in
   const char* what = "geometry/sort launch";
   if ((st = launch_body<ZeroBody>(sink, blocks_for(ncell + 1, 256), 0, {ws.cell_start, ncell + 1}, what)) != SAR_OK)
     return st;
-  if ((st = launch_body<KeysBody<W>>(sink, blocks_for(n_v_grid, 256), 0, {g, ws.key, ws.rank, ws.cell_start},
-                                     what)) != SAR_OK)
-    return st;
-  const int nb = (int)((ncell + kScanChunk - 1) / kScanChunk);
-  int32_t* bsum = ws.cell_start + ncell + 1;
-  if ((st = launch_body<ScanLocalBody>(sink, nb, 0, {ws.cell_start, ncell, bsum}, what)) != SAR_OK) return st;
-  if ((st = launch_body<ScanSumsBody>(sink, 1, 0, {bsum, nb, ws.cell_start + ncell}, what)) != SAR_OK) return st;
-  if ((st = launch_body<ScanAddBody>(sink, nb, 0, {ws.cell_start, ncell, bsum}, what)) != SAR_OK) return st;
-  if ((st = launch_body<ScatterBody>(sink, blocks_for(n_v_grid, 256), 0,
-                                     {n_v, ws.key, ws.rank, ws.cell_start, ws.order}, what)) != SAR_OK)
-    return st;
-  if ((st = launch_body<SortCellsBody>(sink, blocks_for(ncell, 256), 0, {ncell, ws.cell_start, ws.order}, what)) !=
+  if ((st = launch_body<KeysBody<W>>(sink, blocks_for(n_v_grid, 256), 0, {g, ws.key, ws.cell_start}, what)) !=
       SAR_OK)
     return st;
+  // cell starts: exclusive scan of the per-cell counts
+  auto scan = [&](int32_t* data, int64_t n, int32_t* bsum) -> sar_status {
+    const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
+    sar_status s2;
+    if ((s2 = launch_body<ScanLocalBody>(sink, nb, 0, {data, n, bsum}, what)) != SAR_OK) return s2;
+    if ((s2 = launch_body<ScanSumsBody>(sink, 1, 0, {bsum, nb, data + n}, what)) != SAR_OK) return s2;
+    return launch_body<ScanAddBody>(sink, nb, 0, {data, n, bsum}, what);
+  };
+  if ((st = scan(ws.cell_start, ncell, ws.cell_start + ncell + 1)) != SAR_OK) return st;
+  // sorted order: LSD radix passes over the key bits of the largest cell index,
+  // as few as digits of up to 11 bits allow (the histogram stride and the
+  // grids follow n_pos_grid, so a fused batch's launch sequence does not
+  // depend on the call's n_pos)
+  const int ntiles = (int)((n_v_grid + kSortTile - 1) / kSortTile);
+  int bits = 1;
+  while ((int64_t)1 << bits < ncell) ++bits;
+  const int npass = (bits + 10) / 11;
+  const int db = std::max(8, (bits + npass - 1) / npass);
+  for (int q = 0; q < npass && ntiles > 0; ++q) {
+    const int32_t* kin = (q & 1) ? ws.key_alt : ws.key;
+    int32_t* kout = q + 1 == npass ? nullptr : ((q & 1) ? ws.key : ws.key_alt);
+    int32_t* vout = ((npass - 1 - q) & 1) ? ws.order_alt : ws.order;
+    const int32_t* vin = q == 0 ? nullptr : (((npass - q) & 1) ? ws.order_alt : ws.order);
+    switch (db) {
+      case 8: st = radix_pass<8>(sink, kin, vin, kout, vout, n_v, db * q, ntiles, ws.hist, scan); break;
+      case 9: st = radix_pass<9>(sink, kin, vin, kout, vout, n_v, db * q, ntiles, ws.hist, scan); break;
+      case 10: st = radix_pass<10>(sink, kin, vin, kout, vout, n_v, db * q, ntiles, ws.hist, scan); break;
+      default: st = radix_pass<11>(sink, kin, vin, kout, vout, n_v, db * q, ntiles, ws.hist, scan); break;
+    }
+    if (st != SAR_OK) return st;
+  }
   return launch_body<RecordsBody<W>>(sink, blocks_for(n_v_grid, 256), 0,
                                      {g, ws.order, (SampleRec<W>*)ws.rec}, what);
 }

@@ -198,24 +198,33 @@ __device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint
   const int total = __builtin_amdgcn_readfirstlane(seg_off[NSEG]);
   const int nchunk = (total + CH - 1) / CH;
 
-  // sorted-list index of the chunk's lane-th sample (lanes >= chunk size: -1)
+  // sorted-list index of the chunk's lane-th sample (lanes >= chunk size: -1);
+  // chunks are asked for in increasing order, so each lane keeps the segment
+  // it reached last time and only moves forward
+  int kseg = 0;
   auto chunk_index = [&](int c) __attribute__((always_inline)) -> int {
     const int t = c * CH + lane;
     if (lane >= CH || t >= total) return -1;
-    int k = 0;
-    while (seg_off[k + 1] <= t) ++k;
-    return seg_s[k] + (t - seg_off[k]);
+    while (seg_off[kseg + 1] <= t) ++kseg;
+    return seg_s[kseg] + (t - seg_off[kseg]);
   };
   // per-sample fields gathered lane-parallel (lane k: the chunk's k-th sample)
   const SampleRec<W>* __restrict__ grec = (const SampleRec<W>*)a.rec;
   auto gather_beta = [&](int sidx) __attribute__((always_inline)) -> double {
     return sidx >= 0 ? grec[sidx].beta : 0.0;
   };
-  auto gather_idx = [&](int sidx) __attribute__((always_inline)) -> int {
-    if (sidx < 0) return 0;
-    const uint32_t cxy = *(const uint32_t*)&grec[sidx].cx;   // cx low half, cy high half
-    const int aa = ((int)(cxy >> 16) - ty0) & (a.my - 1);    // last-tap row offset in [0, NBY)
-    const int bb = ((int)(cxy & 0xffffu) - tx0) & (a.mx - 1);  // last-tap column offset in [0, NBX)
+  // the last-tap cell (cx low half, cy high half) is gathered a chunk ahead
+  // and turned into the tap pattern only when the chunk is processed: using
+  // the loaded value at once would wait for every earlier vector load,
+  // including the direct loads of the next chunk, and serialise the pipeline
+  auto gather_cxy = [&](int sidx) __attribute__((always_inline)) -> uint32_t {
+    return sidx >= 0 ? *(const uint32_t*)&grec[sidx].cx : 0u;
+  };
+  auto pattern_of = [&](uint32_t cxy) __attribute__((always_inline)) -> int {
+    int aa = (int)(cxy >> 16) - ty0;       // last-tap row offset in [0, NBY) after the wrap
+    int bb = (int)(cxy & 0xffffu) - tx0;   // last-tap column offset in [0, NBX)
+    aa += aa < 0 ? a.my : 0;
+    bb += bb < 0 ? a.mx : 0;
     return aa * NBX + bb;
   };
   // Chunk c into buffer b with direct global-to-LDS loads: the echo rows of
@@ -279,7 +288,7 @@ __device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint
   int sidx0 = chunk_index(0);
   int sidx1 = chunk_index(1);
   double beta0 = gather_beta(sidx0);
-  int idx0 = gather_idx(sidx0);
+  uint32_t cxy0 = gather_cxy(sidx0);
   int src1 = sidx1 >= 0 ? a.order[sidx1] : 0;
   if (nchunk > 0) stage(0, 0, sidx0 >= 0 ? a.order[sidx0] : 0, sidx0);
   for (int c = 0; c < nchunk; ++c) {
@@ -287,6 +296,7 @@ __device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     const int n = __builtin_amdgcn_readfirstlane(min(CH, total - c * CH));
+    const int idx0 = pattern_of(cxy0);
     // compensation in place, two samples at a time (chunks hold an even
     // number of slots; a spare slot is processed but never read):
     // s_hat = s exp(+j 2 pi f beta / c), k * beta in float64 reduced modulo a
@@ -325,7 +335,7 @@ __device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint
     const int sidx2 = chunk_index(c + 2);
     const int src2 = sidx2 >= 0 ? a.order[sidx2] : 0;
     const double beta1 = gather_beta(sidx1);
-    const int idx1 = gather_idx(sidx1);
+    const uint32_t cxy1 = gather_cxy(sidx1);
     // one sample with its tap pattern fixed at compile time: I = row offset *
     // NBX + column offset of its last tap relative to the tile
     int k = 0;
@@ -452,7 +462,7 @@ __device__ __forceinline__ void GridBody<W, ET, TC>::run(const GridArgs& a, uint
     sidx1 = sidx2;
     src1 = src2;
     beta0 = beta1;
-    idx0 = idx1;
+    cxy0 = cxy1;
   }
 
 #pragma unroll

@@ -18,8 +18,10 @@
 // lane takes a contiguous run of frequencies, whose k_z positions are
 // monotone and close together, accumulates them in a small register window of
 // cells and flushes it to the shared grid with LDS atomics, so few lanes hit
-// the same cell at once.  The +-1 factor (-1)^(P+Q) that lets the next step
-// use plain inverse DFTs on centred mode indices is folded in here.
+// the same cell at once.  The +-1 factor (-1)^P (and (-1)^Q) that lets the
+// next step use plain inverse DFTs on centred mode indices of an even axis is
+// folded in here (an odd axis is shifted and phase-corrected by its inverse
+// transform instead).
 
 #include "device_common.hpp"
 #include "launch.hpp"
@@ -44,6 +46,7 @@ struct StoltArgs {
   double dz_cells;             // dz * MZ / (2 pi)
   float es_beta;
   int dcf;             // 1: filter factor 4k (k_z times the Jacobian dk_z/dk = 4k/k_z)
+  int sgx, sgy;        // 1: fold (-1)^P (resp. (-1)^Q) in (even nx, ny)
   int64_t ncol;
 };
 
@@ -142,7 +145,7 @@ __device__ __forceinline__ void StoltBody<MZ, WZ, F32>::run(const StoltArgs& a, 
       const float kxf = (float)(P - a.nx / 2) * (float)a.dkx;
       const float kyf = (float)(Q - a.ny / 2) * (float)a.dky;
       const float kp2f = kxf * kxf + kyf * kyf;
-      const float sgn = ((P + Q) & 1) ? -1.f : 1.f;
+      const float sgn = (((P & a.sgx) ^ (Q & a.sgy)) & 1) ? -1.f : 1.f;
       float2 win[WWIN];
 #pragma unroll
       for (int s2 = 0; s2 < WWIN; ++s2) win[s2] = make_float2(0.f, 0.f);
@@ -268,6 +271,7 @@ struct PlaneArgs {
   double dkx, dky;
   double z_cyc;        // (z0 - Z_0) / (2 pi)
   int dcf;             // 1: filter factor 4k instead of k_z (see StoltArgs)
+  int sgx, sgy;        // lateral sign folding as in StoltArgs
   int64_t ncol;
 };
 
@@ -307,7 +311,7 @@ struct PlaneBody {
         acc.y += __shfl_xor(acc.y, m, G);
       }
       if (live && gl == 0) {
-        const float sgn = ((P + Q) & 1) ? -1.f : 1.f;
+        const float sgn = (((P & a.sgx) ^ (Q & a.sgy)) & 1) ? -1.f : 1.f;
         a.zc[colc] = make_float2(sgn * acc.x, sgn * acc.y);
       }
     }
@@ -348,6 +352,8 @@ sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, Launch
     b.dky = 2.0 * M_PI / (p.ny * p.dy);
     b.z_cyc = (p.z0 - p.z_ref) / (2.0 * M_PI);
     b.dcf = (p.flags & SAR_STOLT_DCF) ? 1 : 0;
+    b.sgx = (p.nx & 1) ? 0 : 1;
+    b.sgy = (p.ny & 1) ? 0 : 1;
     b.ncol = (int64_t)p.nx * p.ny;
     const int64_t ngroups = (b.ncol + 15) / 16;
     const int64_t nblk = ngroups < 256 * 8 ? ngroups : 256 * 8;
@@ -370,6 +376,8 @@ sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, Launch
   a.dz_cells = p.dz * p.mz / (2.0 * M_PI);
   a.es_beta = (float)p.es_beta;
   a.dcf = (p.flags & SAR_STOLT_DCF) ? 1 : 0;
+  a.sgx = (p.nx & 1) ? 0 : 1;
+  a.sgy = (p.ny & 1) ? 0 : 1;
   a.ncol = (int64_t)p.nx * p.ny;
   if (a.ncol == 0) return SAR_OK;
   switch (p.mz) {

@@ -3,7 +3,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +24,14 @@ int next_pow2(int64_t v) {
   int r = 1;
   while (r < v) r <<= 1;
   return r;
+}
+// oversampled lateral grid: the smallest multiple of 8 cells (whole gridding
+// tiles) of the form 2^a 3^b 5^c (a transform length) at or above sigma * n
+int grid_length(int n, double sigma) {
+  int64_t m = (int64_t)std::ceil(sigma * n - 1e-9);
+  m = (m + 7) / 8 * 8;
+  while (!is_5smooth(m)) m += 8;
+  return (int)m;
 }
 
 double bessel_i0_host(double x) {
@@ -114,6 +126,130 @@ double nufft_error_estimate(int W, double sigma) {
   return 5.0 * std::exp(-M_PI * W * std::sqrt(1.0 - 1.0 / sigma));
 }
 
+// Lateral NUFFT parameters for oversampling `up` (host only): grid sizes, the
+// kernel width from the plan's tolerance (unless the descriptor fixed it), the
+// Kaiser-Bessel shape and the default gridding tile.
+sar_status choose_lateral(Plan& p, double up) {
+  const int mx = grid_length(p.nx, up);
+  const int my = grid_length(p.ny, up);
+  if (mx > kMaxFftLength || my > kMaxFftLength)
+    return fail(SAR_ERR_UNSUPPORTED, "oversampled grid of " + std::to_string(mx) + " x " + std::to_string(my) +
+                                         " cells: at most " + std::to_string(kMaxFftLength) + " per axis");
+  p.mx = mx;
+  p.my = my;
+  const double sigma = std::min((double)p.mx / p.nx, (double)p.my / p.ny);
+  if (p.kw_req > 0) {
+    p.w = p.kw_req;
+  } else {
+    p.w = kMaxWidth;
+    for (int w = 3; w <= kMaxWidth; ++w)
+      if (nufft_error_estimate(w, sigma) <= p.tol) {
+        p.w = w;
+        break;
+      }
+  }
+  if ((p.flags & SAR_FP32_ARGS) && (p.w != 4 || p.echo_type != SAR_ECHO_C64))
+    return fail(SAR_ERR_UNSUPPORTED, "SAR_FP32_ARGS is compiled for complex64 echo and a 4-tap lateral kernel");
+  // shape parameter of Beatty, Nishimura and Pauly (2005)
+  const double a = (p.w / sigma) * (sigma - 0.5);
+  p.kb_beta = M_PI * std::sqrt(std::max(a * a - 0.8, 1e-6));
+  // gridding tile: one frequency per lane when the sweep has at most 64
+  // frequencies (two per lane would leave half the lanes idle), else the
+  // 4 x 4 tile; the autotuner may change it by timing
+  p.grid_tile = (p.nf <= 64 && grid_tile_compiled(1, p.w)) ? 1 : 0;
+  return SAR_OK;
+}
+
+// Device tables of the lateral NUFFT (deapodisation, grid twiddles) for the
+// plan's current mx, my, w; replaces earlier ones.  The plan's device must be
+// current.
+sar_status upload_lateral(Plan& p) {
+  const double kb_norm = 1.0 / bessel_i0_host(p.kb_beta);
+  const int W = p.w;
+  const double kbb = p.kb_beta;
+  auto kb = [W, kbb, kb_norm](double x) {
+    const double z = 2.0 * x / W;
+    const double r = 1.0 - z * z;
+    return r > 0 ? bessel_i0_host(kbb * std::sqrt(r)) * kb_norm : 0.0;
+  };
+  const std::vector<double> fx = kernel_ft(kb, W, p.mx, p.nx);
+  const std::vector<double> fy = kernel_ft(kb, W, p.my, p.ny);
+  std::vector<float> deapx(p.nx), deapy(p.ny);
+  for (int i = 0; i < p.nx; ++i) deapx[i] = (float)(1.0 / fx[i]);
+  for (int i = 0; i < p.ny; ++i) deapy[i] = (float)(1.0 / fy[i]);
+  void* old[] = {p.d_deapx, p.d_deapy, p.d_tw_mx, p.d_tw_my};
+  for (void* q : old)
+    if (q) (void)hipFree(q);
+  p.d_deapx = p.d_deapy = nullptr;
+  p.d_tw_mx = p.d_tw_my = nullptr;
+  sar_status st;
+  if ((st = upload(&p.d_deapx, deapx)) != SAR_OK) return st;
+  if ((st = upload(&p.d_deapy, deapy)) != SAR_OK) return st;
+  if ((st = upload(&p.d_tw_mx, twiddles(p.mx, -1))) != SAR_OK) return st;
+  return upload(&p.d_tw_my, twiddles(p.my, -1));
+}
+
+// ---- tuning file: oversampling and gridding tile per size bucket ----------
+// With SAR_AUTOTUNE_FILE naming a file, sar_plan_autotune records its choice
+// for the plan's bucket (image size, sweep length, pair count, echo type,
+// flags, tolerance, shots rounded up to a power of two) and plans created
+// later with upsample = 0 start from it.  One "key = sigma tile" line each.
+std::string tuning_key(const Plan& p, int64_t n_pos) {
+  int b = 0;
+  while (((int64_t)1 << b) < std::max<int64_t>(n_pos, 1)) ++b;
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "n%dx%dx%d f%d p%d e%d fl%u tol%.3g pos2^%d", p.nx, p.ny, p.nz, p.nf, p.n_pair,
+                p.echo_type, p.flags, p.tol, b);
+  return buf;
+}
+
+std::mutex g_tuning_mu;
+
+bool tuning_lookup(const Plan& p, double* sigma, int* tile) {
+  const char* path = std::getenv("SAR_AUTOTUNE_FILE");
+  if (!path || !*path) return false;
+  const std::string key = tuning_key(p, p.max_pos);
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    const size_t eq = line.find(" = ");
+    if (eq == std::string::npos || line.compare(0, eq, key) != 0 || eq != key.size()) continue;
+    double sg = 0;
+    int t = -1;
+    if (std::sscanf(line.c_str() + eq + 3, "%lf %d", &sg, &t) == 2 && sg >= kMinUpsample && sg <= 4) {
+      *sigma = sg;
+      *tile = t;
+      found = true;  // the last entry for a key wins
+    }
+  }
+  return found;
+}
+
+void tuning_store(const Plan& p, int64_t n_pos, double sigma, int tile) {
+  const char* path = std::getenv("SAR_AUTOTUNE_FILE");
+  if (!path || !*path) return;
+  const std::string key = tuning_key(p, n_pos);
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  std::vector<std::string> keep;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line))
+      if (line.compare(0, key.size() + 3, key + " = ") != 0) keep.push_back(line);
+  }
+  char val[64];
+  std::snprintf(val, sizeof(val), "%.6g %d", sigma, tile);
+  keep.push_back(key + " = " + val);
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream o(tmp, std::ios::trunc);
+    for (const auto& l : keep) o << l << "\n";
+  }
+  std::rename(tmp.c_str(), path);
+}
+
 sar_status validate_desc(const sar_plan_desc* d) {
   if (!d) return fail(SAR_ERR_INVALID, "descriptor is NULL");
   if (d->n_tx < 1 || d->n_rx < 1 || !d->tx_xy || !d->rx_xy) return fail(SAR_ERR_INVALID, "array layout missing");
@@ -129,8 +265,9 @@ sar_status validate_desc(const sar_plan_desc* d) {
       return fail(SAR_ERR_INVALID, "frequencies must be strictly increasing");
   }
   auto okn = [](int v, int lo, int hi) { return v >= lo && v <= hi && is_pow2(v); };
-  if (!okn(d->nx, 8, 2048) || !okn(d->ny, 8, 2048))
-    return fail(SAR_ERR_INVALID, "nx, ny must be powers of two in [8, 2048]");
+  auto ok5 = [](int v, int lo, int hi) { return v >= lo && v <= hi && is_5smooth(v); };
+  if (!ok5(d->nx, 8, 2048) || !ok5(d->ny, 8, 2048))
+    return fail(SAR_ERR_INVALID, "nx, ny must be in [8, 2048] and products of 2, 3 and 5");
   if (d->nz != 1 && !okn(d->nz, 2, 512))
     return fail(SAR_ERR_INVALID, "nz must be 1 (one plane) or a power of two in [2, 512]");
   const double g[] = {d->x0, d->y0, d->z0, d->dx, d->dy, d->dz, d->z_ref, d->z_focus};
@@ -145,8 +282,8 @@ sar_status validate_desc(const sar_plan_desc* d) {
   if (d->echo_type != SAR_ECHO_C64 && d->echo_type != SAR_ECHO_F16X2)
     return fail(SAR_ERR_INVALID, "unknown echo type");
   if (!(d->tol == 0 || (d->tol > 0 && d->tol <= 0.1))) return fail(SAR_ERR_INVALID, "tol must be 0 or in (0, 0.1]");
-  if (!(d->upsample == 0 || (d->upsample >= 2 && d->upsample <= 4)))
-    return fail(SAR_ERR_UNSUPPORTED, "upsample must be 0 or in [2, 4]");
+  if (!(d->upsample == 0 || (d->upsample >= kMinUpsample && d->upsample <= 4)))
+    return fail(SAR_ERR_UNSUPPORTED, "upsample must be 0 or in [1.25, 4]");
   if (!(d->kernel_width == 0 || (d->kernel_width >= 3 && d->kernel_width <= kMaxWidth)))
     return fail(SAR_ERR_INVALID, "kernel_width must be 0 or 3..8");
   if (d->flags & ~(SAR_NO_COMPENSATION | SAR_FP32_ARGS | SAR_STOLT_DCF))
@@ -189,31 +326,18 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
   p.xc = p.x0 + (p.nx / 2) * p.dx;
   p.yc = p.y0 + (p.ny / 2) * p.dy;
 
-  // lateral NUFFT: power-of-two oversampled grid, Kaiser-Bessel kernel
-  const double up = d->upsample > 0 ? d->upsample : 2.0;
-  p.mx = next_pow2((int64_t)std::ceil(up * p.nx - 1e-9));
-  p.my = next_pow2((int64_t)std::ceil(up * p.ny - 1e-9));
-  if (p.mx > kMaxFftLength || p.my > kMaxFftLength)
-    return fail(SAR_ERR_UNSUPPORTED, "oversampled grid of " + std::to_string(p.mx) + " x " + std::to_string(p.my) +
-                                         " cells: at most " + std::to_string(kMaxFftLength) + " per axis");
-  const double sigma = std::min((double)p.mx / p.nx, (double)p.my / p.ny);
-  if (d->kernel_width > 0) {
-    p.w = d->kernel_width;
-  } else {
-    p.w = kMaxWidth;
-    for (int w = 3; w <= kMaxWidth; ++w)
-      if (nufft_error_estimate(w, sigma) <= p.tol) {
-        p.w = w;
-        break;
-      }
+  // lateral NUFFT: the requested oversampling, else the one tuned for this
+  // plan's size bucket (sar_plan_autotune with a tuning file), else 2
+  p.up_req = d->upsample;
+  p.kw_req = d->kernel_width;
+  double up = d->upsample > 0 ? d->upsample : 2.0;
+  int tuned_tile = -1;
+  if (d->upsample == 0 && d->n_slabs <= 1) {
+    double tuned_up = 0;
+    if (tuning_lookup(p, &tuned_up, &tuned_tile)) up = tuned_up;
   }
-  if ((p.flags & SAR_FP32_ARGS) && (p.w != 4 || p.echo_type != SAR_ECHO_C64))
-    return fail(SAR_ERR_UNSUPPORTED, "SAR_FP32_ARGS is compiled for complex64 echo and a 4-tap lateral kernel");
-  // shape parameter of Beatty, Nishimura and Pauly (2005)
-  {
-    const double a = (p.w / sigma) * (sigma - 0.5);
-    p.kb_beta = M_PI * std::sqrt(std::max(a * a - 0.8, 1e-6));
-  }
+  if ((st = choose_lateral(p, up)) != SAR_OK) return st;
+  if (tuned_tile >= 0 && grid_tile_compiled(tuned_tile, p.w)) p.grid_tile = tuned_tile;
   // Stolt NUFFT: oversampled LDS grid, exponential-of-semicircle kernel
   p.mz = std::max(64, next_pow2(2 * (int64_t)p.nz));  // 64 .. 1024 cells
   p.wz = p.tol < 1e-5 ? 8 : 6;
@@ -226,11 +350,6 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
     p.beta_sign = 2.0 * (p.z_ref > p.z_focus ? 1.0 : -1.0);
     p.inv4rc = 1.0 / (4.0 * std::fabs(p.z_focus - p.z_ref));
   }
-
-  // gridding tile: one frequency per lane when the sweep has at most 64
-  // frequencies (two per lane would leave half the lanes idle), else the
-  // 4 x 4 tile; the autotuner may change it by timing
-  p.grid_tile = (p.nf <= 64 && grid_tile_compiled(1, p.w)) ? 1 : 0;
 
   // ---- tables ----
   std::vector<double> fcc(p.nf), kk(p.nf);
@@ -251,14 +370,6 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
       pair[4 * l + 2] = (sx * sx + sy * sy) * p.inv4rc;
       pair[4 * l + 3] = 0.0;
     }
-  const double kb_norm = 1.0 / bessel_i0_host(p.kb_beta);
-  const int W = p.w;
-  const double kbb = p.kb_beta;
-  auto kb = [W, kbb, kb_norm](double x) {
-    const double z = 2.0 * x / W;
-    const double r = 1.0 - z * z;
-    return r > 0 ? bessel_i0_host(kbb * std::sqrt(r)) * kb_norm : 0.0;
-  };
   const int WZ = p.wz;
   const double esb = p.es_beta;
   auto es = [WZ, esb](double x) {
@@ -266,18 +377,23 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
     const double r = 1.0 - z * z;
     return r > 0 ? std::exp(esb * (std::sqrt(r) - 1.0)) : 0.0;
   };
-  const std::vector<double> fx = kernel_ft(kb, W, p.mx, p.nx);
-  const std::vector<double> fy = kernel_ft(kb, W, p.my, p.ny);
   const std::vector<double> fz = kernel_ft(es, WZ, p.mz, p.nz);
-  std::vector<float> deapx(p.nx), deapy(p.ny), deapz(p.nz), signx(p.nx), signy(p.ny);
-  for (int i = 0; i < p.nx; ++i) {
-    deapx[i] = (float)(1.0 / fx[i]);
-    signx[i] = ((i + p.nx / 2) & 1) ? -1.f : 1.f;
-  }
-  for (int i = 0; i < p.ny; ++i) {
-    deapy[i] = (float)(1.0 / fy[i]);
-    signy[i] = ((i + p.ny / 2) & 1) ? -1.f : 1.f;
-  }
+  std::vector<float> deapz(p.nz), signx(p.nx), signy(p.ny);
+  for (int i = 0; i < p.nx; ++i) signx[i] = ((i + p.nx / 2) & 1) ? -1.f : 1.f;
+  for (int i = 0; i < p.ny; ++i) signy[i] = ((i + p.ny / 2) & 1) ? -1.f : 1.f;
+  // odd sides: the inverse transform of centred modes P = p + h (h = n / 2)
+  // at voxel u is exp(-j 2 pi h (u - h) / n) times the plain inverse DFT at
+  // (u - h) mod n; the factor in float64, rounded once
+  auto post = [](int n) {
+    std::vector<float2> t(n);
+    const int h = n / 2;
+    for (int u = 0; u < n; ++u) {
+      const int64_t e = ((int64_t)h * (u - h)) % n;
+      const double ang = -2.0 * M_PI * (double)e / (double)n;
+      t[u] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    return t;
+  };
   for (int i = 0; i < p.nz; ++i) deapz[i] = (float)(1.0 / fz[i]);
 
   hipError_t e = hipSetDevice(device);
@@ -298,13 +414,12 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
       }
     if ((st = upload(&p.d_txrx, txrx)) != SAR_OK) return st;
   }
-  if ((st = upload(&p.d_deapx, deapx)) != SAR_OK) return st;
-  if ((st = upload(&p.d_deapy, deapy)) != SAR_OK) return st;
+  if ((st = upload_lateral(p)) != SAR_OK) return st;
   if ((st = upload(&p.d_deapz, deapz)) != SAR_OK) return st;
   if ((st = upload(&p.d_signx, signx)) != SAR_OK) return st;
   if ((st = upload(&p.d_signy, signy)) != SAR_OK) return st;
-  if ((st = upload(&p.d_tw_mx, twiddles(p.mx, -1))) != SAR_OK) return st;
-  if ((st = upload(&p.d_tw_my, twiddles(p.my, -1))) != SAR_OK) return st;
+  if ((p.nx & 1) && (st = upload(&p.d_postx, post(p.nx))) != SAR_OK) return st;
+  if ((p.ny & 1) && (st = upload(&p.d_posty, post(p.ny))) != SAR_OK) return st;
   if ((st = upload(&p.d_tw_nx, twiddles(p.nx, +1))) != SAR_OK) return st;
   if ((st = upload(&p.d_tw_ny, twiddles(p.ny, +1))) != SAR_OK) return st;
   if ((st = upload(&p.d_tw_mz, twiddles(p.mz, +1))) != SAR_OK) return st;
@@ -335,7 +450,7 @@ void free_plan(Plan& p) {
   for (auto& sub : p.slabs) free_plan(*sub);
   p.slabs.clear();
   void* ptrs[] = {p.d_fcc, p.d_k, p.d_pair, p.d_txrx, p.d_deapx, p.d_deapy, p.d_deapz, p.d_signx,
-                  p.d_signy, p.d_tw_mx, p.d_tw_my, p.d_tw_nx, p.d_tw_ny, p.d_tw_mz};
+                  p.d_signy, p.d_postx, p.d_posty, p.d_tw_mx, p.d_tw_my, p.d_tw_nx, p.d_tw_ny, p.d_tw_mz};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (hipEvent_t ev : p.events) (void)hipEventDestroy(ev);
@@ -365,10 +480,14 @@ size_t workspace_bytes(const Plan& p, int64_t n_pos, Workspace* ws, char* base) 
     off = al(off + bytes);
     return o;
   };
+  // radix sort: up to 2^11 digit counts per tile of 4096 samples, scanned in place
+  const int64_t nhist = 2048 * ((n_v + 4095) / 4096);
   const size_t o_cell = take((size_t)(ncell + 1 + nscan) * 4);
   const size_t o_key = take((size_t)n_v * 4);
-  const size_t o_rank = take((size_t)n_v * 4);
+  const size_t o_key2 = take((size_t)n_v * 4);
   const size_t o_order = take((size_t)n_v * 4);
+  const size_t o_order2 = take((size_t)n_v * 4);
+  const size_t o_hist = take((size_t)(nhist + 1 + (nhist + 4095) / 4096) * 4);
   const size_t o_rec = take((size_t)n_v * rec_bytes(p.w));
   const int64_t a_elems = std::max((int64_t)p.mx * p.my * p.nf, (int64_t)p.nx * p.ny * p.nz);
   const int64_t b_elems = std::max((int64_t)p.my * p.nx * p.nf, (int64_t)p.nx * p.ny * p.nz);
@@ -377,8 +496,10 @@ size_t workspace_bytes(const Plan& p, int64_t n_pos, Workspace* ws, char* base) 
   if (ws && base) {
     ws->cell_start = (int32_t*)(base + o_cell);
     ws->key = (int32_t*)(base + o_key);
-    ws->rank = (int32_t*)(base + o_rank);
+    ws->key_alt = (int32_t*)(base + o_key2);
     ws->order = (int32_t*)(base + o_order);
+    ws->order_alt = (int32_t*)(base + o_order2);
+    ws->hist = (int32_t*)(base + o_hist);
     ws->rec = (void*)(base + o_rec);
     ws->region_a = (float2*)(base + o_a);
     ws->region_b = (float2*)(base + o_b);

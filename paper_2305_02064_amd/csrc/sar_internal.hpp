@@ -23,6 +23,7 @@ constexpr bool grid_tile_compiled(int tile, int w) {
 }
 constexpr int kMaxWidth = 8;    // largest lateral kernel width
 constexpr int kMaxFftLength = 4096;  // longest lateral transform (oversampled grid side)
+constexpr double kMinUpsample = 1.25;  // smallest lateral oversampling
 // back-projection refuses plans and scans above this many terms
 // (virtual samples x frequencies x voxels), about a second of one GPU
 constexpr double kMaxBackprojectionTerms = 1.0e12;
@@ -51,6 +52,8 @@ struct Plan {
   int echo_type = SAR_ECHO_C64;
   double tol = 1e-4;
   uint32_t flags = 0;
+  double up_req = 0;         // descriptor's upsample (0: automatic)
+  int kw_req = 0;            // descriptor's kernel_width (0: from tol)
   // derived
   double xc = 0, yc = 0;     // lateral centre of the image grid
   int mx = 0, my = 0, w = 0; // oversampled lateral grid and KB width
@@ -67,8 +70,10 @@ struct Plan {
   float* d_deapx = nullptr;    // 1 / phi_hat_x(p), p = -nx/2 .. [nx]
   float* d_deapy = nullptr;    // [ny]
   float* d_deapz = nullptr;    // 1 / phi_hat_z(m), m = -nz/2 .. [nz]
-  float* d_signx = nullptr;    // (-1)^(u + nx/2) [nx]
-  float* d_signy = nullptr;    // (-1)^(v + ny/2) [ny]
+  float* d_signx = nullptr;    // (-1)^(u + nx/2) [nx] (even nx)
+  float* d_signy = nullptr;    // (-1)^(v + ny/2) [ny] (even ny)
+  float2* d_postx = nullptr;   // exp(-j 2 pi h (u - h) / nx), h = nx/2 [nx] (odd nx)
+  float2* d_posty = nullptr;   // likewise for odd ny
   float2* d_tw_mx = nullptr;   // exp(-j 2 pi i / mx) [mx]
   float2* d_tw_my = nullptr;
   float2* d_tw_nx = nullptr;   // exp(+j 2 pi i / nx) [nx]
@@ -90,16 +95,24 @@ struct Plan {
 };
 
 struct Workspace {
-  int32_t* cell_start = nullptr;  // [mx*my + 1]
-  int32_t* key = nullptr;         // [n_v]
-  int32_t* rank = nullptr;        // [n_v]
-  int32_t* order = nullptr;       // [n_v]
+  int32_t* cell_start = nullptr;  // [mx*my + 1] (+ scan partial sums)
+  int32_t* key = nullptr;         // [n_v] sort keys, and their second buffer
+  int32_t* key_alt = nullptr;     // [n_v]
+  int32_t* order = nullptr;       // [n_v] source index of each sorted sample
+  int32_t* order_alt = nullptr;   // [n_v]
+  int32_t* hist = nullptr;        // radix digit histograms (+ scan partial sums)
   void* rec = nullptr;            // [n_v] SampleRec<w>
   float2* region_a = nullptr;     // oversampled grid / spectrum / first inverse pass
   float2* region_b = nullptr;     // x-transformed grid / z profiles
 };
 
 size_t workspace_bytes(const Plan& p, int64_t n_pos, Workspace* ws, char* base);
+
+// lateral NUFFT parameters for an oversampling (host only), their device
+// tables, and the tuning file (plan.cpp)
+sar_status choose_lateral(Plan& p, double up);
+sar_status upload_lateral(Plan& p);
+void tuning_store(const Plan& p, int64_t n_pos, double sigma, int tile);
 
 // error helpers
 void set_error(const std::string& msg);
@@ -128,12 +141,20 @@ struct FftLines {
   int64_t B;
   int64_t s_in_o, s_in_l, s_out_o, s_out_k;
   int n_out;
+  // output placement: 0 natural (P = k); 1 centred crop to n_out modes,
+  // P = k + h for k < n_out - h and P = k - L + h for k >= L - h (h = n_out / 2,
+  // floor); 2 shift by h (P = (k + h) mod L, n_out = L) with the complex
+  // per-output factor cscale[P]: the inverse transform on centred modes of an
+  // odd length
   int centred;
   int sign;  // -1 forward, +1 inverse
-  const float* scale;
+  const float* scale;    // real per-output factor (may be null)
+  const float2* cscale;  // complex per-output factor (centred == 2)
   const float2* tw;  // exp(sign j 2 pi i / L), i < L
   int nt_out;        // non-temporal stores (an output no later kernel reads soon)
 };
+// lengths of the lateral transforms: products 2^a 3^b 5^c
+bool is_5smooth(int64_t v);
 sar_status launch_fft_lines(const FftLines& a, LaunchSink& sink);
 sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, LaunchSink& sink);
 sar_status launch_backprojection(const Plan& p, const double* d_pos, int64_t n_pos, const void* d_echo,

@@ -171,16 +171,18 @@ def _check_scan(info, pos, n_pos, echo):
     n_pos = int(n_pos)
     if not isinstance(pos, torch.Tensor) or not isinstance(echo, torch.Tensor):
         raise TypeError("pos and echo must be torch tensors")
-    if pos.dtype != torch.float64 or tuple(pos.shape) != (n_pos, 3):
-        raise ValueError(f"pos must be float64 of shape ({n_pos}, 3), got {pos.dtype} {tuple(pos.shape)}")
+    # buffers may hold more shots than the call uses (the library reads the
+    # first n_pos), never fewer
+    if pos.dtype != torch.float64 or pos.dim() != 2 or pos.shape[1] != 3 or pos.shape[0] < n_pos:
+        raise ValueError(f"pos must be float64 of shape (>= {n_pos}, 3), got {pos.dtype} {tuple(pos.shape)}")
     n_val = n_pos * info.n_pair * info.n_freq
     if info.echo_type == SAR_ECHO_C64:
-        ok = (echo.dtype == torch.complex64 and echo.numel() == n_val) or \
-             (echo.dtype == torch.float32 and echo.numel() == 2 * n_val)
-        want = f"complex64 with {n_val} values (or float32 with {2 * n_val})"
+        ok = (echo.dtype == torch.complex64 and echo.numel() >= n_val) or \
+             (echo.dtype == torch.float32 and echo.numel() >= 2 * n_val)
+        want = f"complex64 with >= {n_val} values (or float32 with >= {2 * n_val})"
     else:
-        ok = echo.dtype == torch.float16 and echo.numel() == 2 * n_val
-        want = f"float16 with {2 * n_val} values (real/imaginary pairs)"
+        ok = echo.dtype == torch.float16 and echo.numel() >= 2 * n_val
+        want = f"float16 with >= {2 * n_val} values (real/imaginary pairs)"
     if not ok:
         raise ValueError(f"echo must be {want} for this plan ({n_pos} shots x {info.n_pair} pairs x "
                          f"{info.n_freq} frequencies), got {echo.dtype} with {echo.numel()}")

@@ -15,6 +15,7 @@ from .scans import (  # noqa: F401
     awr1443_layout,
     sweep,
     config1_scan,
+    clustered_scan,
     config2_geometry,
     config2_scan,
     config4_scan,

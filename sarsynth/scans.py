@@ -237,6 +237,24 @@ def config1_scan(seed: int = 0, snr_db: float = 20.0, with_echo: bool = True) ->
     return scan
 
 
+def clustered_scan(seed: int = 0, n_dwell: int = 4608, snr_db: float = 20.0) -> Scan:
+    """The tiny scan's 512 shots plus n_dwell shots at one position (a hand
+    that pauses in the middle of the aperture, the extreme of irregular
+    freehand sampling): every pair of those shots lands on the same virtual
+    element, so eight cells of the gridding grid hold n_dwell samples each.
+    Scene, sweep and image as the tiny scan."""
+    base = config1_scan(seed, snr_db, with_echo=False)
+    rng = _rng(6, seed)
+    dwell = np.tile(base.pos[len(base.pos) // 2], (n_dwell, 1))
+    pos = np.concatenate([base.pos, dwell], axis=0)
+    scan = Scan(pos=pos, tx_xy=base.tx_xy, rx_xy=base.rx_xy, freq=base.freq, grid=base.grid,
+                targets=base.targets, amps=base.amps,
+                meta={"config": f"clustered-tiny+{n_dwell}", "seed": seed, "snr_db": snr_db})
+    e = synth_echo_numpy(pos, base.tx_xy, base.rx_xy, base.freq, base.targets, base.amps)
+    scan.echo = add_noise_numpy(e, snr_db, rng).astype(np.complex64)
+    return scan
+
+
 def config2_geometry(seed: int = 0, n_rows: int = 256, n_cols: int = 512, n_freq: int = 256,
                      nz: int = 256) -> Scan:
     """Large freehand scan geometry and scene (no echo): n_rows serpentine rows
@@ -290,8 +308,8 @@ def config2_scan(seed: int = 0, device=None, snr_db: float = 20.0, **kw) -> Scan
 
 
 def _snap_235(s: int, lo: int = 64, hi: int = 256) -> int:
-    """Nearest even 2^a 3^b 5^c in [lo, hi] (ties to the smaller)."""
-    cands = sorted({2 ** a * 3 ** b * 5 ** c for a in range(1, 9) for b in range(0, 6) for c in range(0, 4)
+    """Nearest 2^a 3^b 5^c in [lo, hi] (ties to the smaller)."""
+    cands = sorted({2 ** a * 3 ** b * 5 ** c for a in range(0, 9) for b in range(0, 6) for c in range(0, 4)
                     if lo <= 2 ** a * 3 ** b * 5 ** c <= hi})
     return min(cands, key=lambda v: (abs(v - s), v))
 
@@ -300,9 +318,8 @@ def config4_scan(seed: int, with_echo: bool = True, device=None) -> Scan:
     """One scan of the uneven batch: side s log-uniform in [64, 256] snapped to
     a 2^a 3^b 5^c size, s x s positions at lambda/4, N_f in {64, 128, 256},
     smooth z deviation scaled to max |d_z| = A ~ U(1, 2) cm, 20-100 points at
-    z in [0.2, 0.5] m.  The image covers the aperture: S x S x N_f voxels at
-    lambda/4 laterally with S the power of two at or above s (the library's
-    lateral transforms are power-of-two), z in [0.2, 0.5)."""
+    z in [0.2, 0.5] m.  The image is sized to the aperture: s x s x N_f voxels
+    at lambda/4 laterally, centred on it, z in [0.2, 0.5)."""
     rng = _rng(4, seed)
     lam = LAMBDA_C
     pitch = lam / 4
@@ -325,7 +342,7 @@ def config4_scan(seed: int, with_echo: bool = True, device=None) -> Scan:
     tgt = np.stack([rng.uniform(-0.4 * ext, 0.4 * ext, nt), rng.uniform(-0.4 * ext, 0.4 * ext, nt),
                     rng.uniform(0.2, 0.5, nt)], axis=1)
     amp = (rng.standard_normal(nt) + 1j * rng.standard_normal(nt)) / np.sqrt(2)
-    side = 1 << int(np.ceil(np.log2(s)))
+    side = s
     grid = ImageGrid(nx=side, ny=side, nz=nf, x0=-(side // 2) * pitch, y0=-(side // 2) * pitch, z0=0.2,
                      dx=pitch, dy=pitch, dz=0.3 / nf, z_ref=0.0, z_focus=0.35)
     scan = Scan(pos=pos, tx_xy=tx, rx_xy=rx, freq=freq, grid=grid, targets=tgt, amps=amp,

@@ -44,8 +44,9 @@ def _desc_kwargs(**over):
 
 
 @pytest.mark.parametrize("bad,needle", [
-    (dict(nx=30), "powers of two"),
-    (dict(ny=4), "powers of two"),
+    (dict(nx=28), "products of 2, 3 and 5"),
+    (dict(ny=4), "products of 2, 3 and 5"),
+    (dict(nx=4096), "products of 2, 3 and 5"),
     (dict(nz=3), "nz"),
     (dict(freq_hz=np.array([78e9, 77e9])), "increasing"),
     (dict(freq_hz=np.array([77e9, np.nan])), "finite"),
@@ -79,11 +80,13 @@ def test_fp32_args_diagnostic_limits(bad):
     assert "SAR_FP32_ARGS" in str(ei.value)
 
 
-def test_upsample_out_of_range_is_unsupported():
+@pytest.mark.parametrize("up", [1.2, 4.5])
+def test_upsample_out_of_range_is_unsupported(up):
     sar = _sar()
     with pytest.raises(sar.SarError) as ei:
-        sar.sar_plan_create(**_desc_kwargs(upsample=1.5))
+        sar.sar_plan_create(**_desc_kwargs(upsample=up))
     assert ei.value.status == sar.SAR_ERR_UNSUPPORTED
+    assert "1.25" in str(ei.value)
 
 
 def test_null_arguments():
@@ -168,7 +171,7 @@ def test_wrappers_check_scan_inputs_against_the_plan(case):
     if case == "pos_flat":
         pos = pos.reshape(-1)
     elif case == "pos_rows":
-        pos = torch.zeros((n + 1, 3), dtype=torch.float64)
+        pos = torch.zeros((n - 1, 3), dtype=torch.float64)
     elif case == "pos_dtype":
         pos = pos.float()
     elif case == "echo_size":
@@ -191,6 +194,8 @@ def test_wrappers_accept_matching_inputs_and_check_outputs(monkeypatch):
     sar._check_scan(info, torch.zeros((3, 3), dtype=torch.float64), 3, torch.zeros((3, 2, 5, 2), dtype=torch.float32))
     h = _fake_info(sar, echo_type=sar.SAR_ECHO_F16X2)
     sar._check_scan(h, torch.zeros((3, 3), dtype=torch.float64), 3, torch.zeros((3, 2, 5, 2), dtype=torch.float16))
+    # larger buffers than the call uses are fine (the first n_pos shots are read)
+    sar._check_scan(info, torch.zeros((5, 3), dtype=torch.float64), 3, torch.zeros((5, 2, 5), dtype=torch.complex64))
     assert sar._image_shape(info) == (8, 16, 4) and sar._spectrum_shape(info) == (16, 8, 5)
     # a wrong image shape is caught before the library call
     calls = []

@@ -136,6 +136,45 @@ def test_largest_transform_lengths(torch_cuda, nx, ny):
     assert err <= IMAGE_TOL
 
 
+@pytest.mark.parametrize("nx,ny", [(72, 100), (75, 81), (150, 250), (250, 64), (135, 243), (125, 225)])
+def test_mixed_radix_image_sides(torch_cuda, nx, ny):
+    # image sides of the form 2^a 3^b 5^c, odd ones included: oversampled grids
+    # of 2^a 3^b 5^c cells (multiples of 8), the mixed-radix line transforms,
+    # the odd-length centred crop and the shifted, phase-corrected inverse
+    grid = ImageGrid(nx=nx, ny=ny, nz=8, x0=-(nx // 2) * 1e-3, y0=-(ny // 2) * 1e-3, z0=0.25, dx=1e-3, dy=1e-3,
+                     dz=0.01, z_ref=0.0, z_focus=0.3)
+    scan = _ragged_scan(500 + nx + ny, 149, 12, grid)
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, grid)
+    plan = make_plan(scan)
+    pos, echo, _ = to_device(scan)
+    img = plan.reconstruct(pos, echo).cpu().numpy()
+    info = plan.info
+    plan.close()
+    err = rel_l2(img, ref)
+    print(f"sides {nx} x {ny} (grid {info['mx']} x {info['my']}): image rel-L2 {err:.3e}")
+    assert info["mx"] % 8 == 0 and info["my"] % 8 == 0 and info["mx"] >= 2 * nx and info["my"] >= 2 * ny
+    assert err <= IMAGE_TOL
+    assert peak_ok(img, ref)
+
+
+@pytest.mark.parametrize("upsample", [1.25, 1.5])
+def test_oversampling_below_two(torch_cuda, tiny, upsample):
+    # sigma in [1.25, 2): grids of 2^a 3^b 5^c cells (40 and 48 cells
+    # for 32 voxels), kernel widths from the plan's tolerance
+    scan, spec_ref, img_ref = tiny
+    plan = make_plan(scan, upsample=upsample)
+    pos, echo, _ = to_device(scan)
+    spec = plan.spectrum(pos, echo).cpu().numpy()
+    img = plan.reconstruct(pos, echo).cpu().numpy()
+    info = plan.info
+    e_s, e_i = rel_l2(spec, spec_ref), rel_l2(img, img_ref)
+    print(f"upsample {upsample}: grid {info['mx']} x {info['my']}, sigma {info['sigma_x']:.3f}, width "
+          f"{info['width']}: spectrum {e_s:.3e}, image {e_i:.3e}")
+    assert info["sigma_x"] >= upsample and info["sigma_x"] < 2
+    assert e_s <= IMAGE_TOL and e_i <= IMAGE_TOL
+    assert peak_ok(img, img_ref)
+
+
 def test_long_sweep(torch_cuda):
     # 700 frequencies: each Stolt lane's run spans several load batches with a
     # partial last one, and the gridding's frequency chunks end mid-wave
@@ -223,6 +262,29 @@ def test_stolt_jacobian_flag(torch_cuda, tiny, nz):
     assert peak_ok(img, ref)
     plain = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, g)
     assert rel_l2(plain, ref) > 0.05   # the flag changes the image
+
+
+def test_clustered_scan_matches_oracle(torch_cuda):
+    # 4608 of 5120 shots at one position: eight cells of 4608 samples each
+    # (more than one 4096-sample tile of the radix sort), the tiles over them
+    # walk long runs; the image must still match the oracle and be reproducible.
+    # With nine tenths of the samples on eight virtual elements the lateral
+    # NUFFT error is that of a few single points, not the average over spread
+    # samples that the tolerance is calibrated on (a single point at a poor
+    # sub-cell offset reaches about 8e-4 per axis with the 4-tap kernel), so
+    # this plan asks for tol 1e-4 (5 taps) to meet the 1e-3 image bar.
+    from sarsynth import clustered_scan
+    scan = clustered_scan(0)
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, scan.grid)
+    plan = make_plan(scan, tol=1e-4)
+    pos, echo, _ = to_device(scan)
+    a = plan.reconstruct(pos, echo).cpu().numpy()
+    b = plan.reconstruct(pos, echo).cpu().numpy()
+    err = rel_l2(a, ref)
+    print(f"clustered scan ({scan.n_pos} shots, 4608 at one position): rel-L2 {err:.3e}")
+    assert err <= IMAGE_TOL
+    assert peak_ok(a, ref)
+    assert np.array_equal(a, b)
 
 
 def test_empty_scan_gives_zero_image(torch_cuda, tiny):
