@@ -202,6 +202,19 @@ sar_status sar_plan_get_info(sar_plan plan, sar_plan_info* info);
 sar_status sar_reconstruct(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,
                            float echo_scale, void* d_image, void* d_workspace, sar_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * pipeline as sar_reconstruct with no workspace argument.  Its workspace is a
+ * fixed array of SAR_NOALLOC_SCRATCH_BYTES in the library's device memory, one
+ * per device, held until the process ends; the call allocates nothing.
+ * Scans whose workspace (sar_plan_workspace_bytes) exceeds it return
+ * SAR_ERR_UNSUPPORTED with nothing queued.  Calls that overlap on one device
+ * (several streams or host threads) share the array and race; serialise them.
+ * Other arguments, ordering and errors as sar_reconstruct. */
+#define SAR_NOALLOC_SCRATCH_BYTES (64u << 20)
+sar_status sar_reconstruct_noalloc(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,
+                                   float echo_scale, void* d_image, sar_stream_t stream);
+
 /* Steps a0-a3 only: the compensated spatial spectrum S, written to
  * d_spectrum (device float2 [ny][nx][n_freq], centred mode order). */
 sar_status sar_spectrum(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,

@@ -19,7 +19,7 @@ OUT = os.path.join(PKG, "libsar.so")
 BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["k_grid_w8.hip", "k_grid_w7.hip", "k_grid_w6.hip", "k_grid_w5.hip", "k_grid_w4.hip", "k_grid_w3.hip",
-           "k_fft.hip", "k_stolt.hip", "k_geometry.hip", "k_bpa.hip", "k_grid.cpp", "plan.cpp", "api.cpp", "server.cpp", "batch.cpp"]
+           "k_fft.hip", "k_stolt.hip", "k_geometry.hip", "k_bpa.hip", "k_grid.cpp", "plan.cpp", "api.cpp", "server.cpp", "batch.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -99,6 +99,7 @@ def library():
         "sar_plan_get_info": ([vp, ctypes.POINTER(sar_plan_info)], i32),
         "sar_reconstruct": ([vp, vp, i64, vp, f32, vp, vp, vp], i32),
         "sar_spectrum": ([vp, vp, i64, vp, f32, vp, vp, vp], i32),
+        "sar_reconstruct_noalloc": ([vp, vp, i64, vp, f32, vp, vp], i32),
         "sar_image_from_spectrum": ([vp, vp, vp, vp, vp], i32),
         "sar_plan_set_timing": ([vp, ctypes.c_int], i32),
         "sar_plan_autotune": ([vp, vp, i64, vp, f32, vp, vp, ctypes.POINTER(i32)], i32),
@@ -251,6 +252,15 @@ def sar_reconstruct(plan, pos, n_pos, echo, echo_scale, image, workspace, stream
             _dptr(image, "image", torch.complex64, _image_shape(info)), _dptr(workspace, "workspace"))
     _check_workspace(plan, n_pos, workspace)
     _check(library().sar_reconstruct(plan, *args, _stream(stream)))
+
+
+def sar_reconstruct_noalloc(plan, pos, n_pos, echo, echo_scale, image, stream=None):
+    """sar_reconstruct with the library's fixed scratch as workspace (no allocation)."""
+    info = _info(plan)
+    _check_scan(info, pos, n_pos, echo)
+    args = (_dptr(pos, "pos", torch.float64), int(n_pos), _dptr(echo, "echo"), float(echo_scale),
+            _dptr(image, "image", torch.complex64, _image_shape(info)))
+    _check(library().sar_reconstruct_noalloc(plan, *args, _stream(stream)))
 
 
 def sar_spectrum(plan, pos, n_pos, echo, echo_scale, spectrum, workspace, stream=None):
