@@ -110,26 +110,37 @@ __device__ __forceinline__ void FftBody<L1, L2, BC, SIGN>::run(const FftLines& a
 // ---------------------------------------------------------------------------
 // Any length 2^a 3^b 5^c (the non-power-of-two image sides and oversampled
 // grids): a block holds BC batch columns of the whole line in LDS and runs
-// self-sorting (Stockham) radix-8/4/2/3/5 passes between two LDS buffers.  Pass
-// p with radix R, after passes whose radices multiply to Ns, maps butterfly j
-// (k = j mod Ns) from x[j + q L/R] to y[(j / Ns) Ns R + k + q Ns] after the
-// twiddles w_{Ns R}^(q k) and an R-point DFT; the last pass leaves X in natural
-// order.  The epilogue is that of the power-of-two kernel plus the shifted,
-// complex-scaled placement of odd inverse lengths.
+// self-sorting (Stockham) radix-8/4/2/3/5 passes on it.  Pass p with radix R,
+// after passes whose radices multiply to Ns, maps butterfly j (k = j mod Ns)
+// from x[j + q L/R] to x'[(j / Ns) Ns R + k + q Ns] after the twiddles
+// w_{Ns R}^(q k) and an R-point DFT; the last pass leaves X in natural order.
+// Each pass reads all its butterflies into registers, waits for the block, and
+// writes them back, so one LDS buffer serves in place; every thread issues all
+// its global loads (at most 32) before using any.  The epilogue is that of the
+// power-of-two kernel plus the shifted, complex-scaled placement of odd
+// inverse lengths.
 constexpr int kMixMaxPasses = 16;
-constexpr int kMixThreads = 256;
-constexpr int kMixMaxElems = 8192;  // L x BC complex values per LDS buffer
+constexpr int kMixThreads = 512;
+constexpr int kMixMaxElems = 4096;                        // L x BC complex values in LDS
+constexpr int kMixPerThread = kMixMaxElems / kMixThreads;  // 8
 
 struct FftMixedArgs {
   FftLines f;
-  int lbc;  // log2 of the batch columns per block
+  int lbc;    // log2 of the batch columns per block
   int npass;
-  int rad[kMixMaxPasses];
+  uint64_t radices;  // radix of pass p in bits [4p, 4p + 4) (no per-pass array:
+                     // a fused batch copies its arguments to registers)
   // n / d as umulhi(n, ceil(2^32 / d)), exact for n < 2^16, d <= 4096 (checked
-  // exhaustively): the pass's Ns (0 when Ns = 1) and the length
-  uint32_t mag_ns[kMixMaxPasses];
+  // exhaustively); this one for the length, the passes' Ns computed in the kernel
   uint32_t mag_l;
 };
+
+// ceil(2^32 / d) for 2 <= d <= 4096 (0 for d = 1): in float64 the quotient is
+// exact when d is a power of two and otherwise at least 1/d from an integer,
+// far more than its rounding, so the ceiling is exact
+__device__ __forceinline__ uint32_t magic_div(int d) {
+  return d <= 1 ? 0u : (uint32_t)ceil(4294967296.0 / (double)d);
+}
 
 // R-point DFT in natural order, X[m] = sum_n a[n] exp(SIGN j 2 pi n m / R)
 template <int R, int SIGN>
@@ -158,81 +169,102 @@ __device__ __forceinline__ void small_dft(float2 (&a)[R]) {
 }
 
 template <int R, int SIGN>
-__device__ __forceinline__ void stockham_pass(const float2* __restrict__ x, float2* __restrict__ y, int L, int lbc,
-                                              int Ns, uint32_t mag_ns, uint32_t mag_l,
-                                              const float2* __restrict__ tw) {
+__device__ __forceinline__ void stockham_pass(float2* __restrict__ x, int L, int lbc, int Ns, uint32_t mag_ns,
+                                              uint32_t mag_l, const float2* __restrict__ tw) {
+  constexpr int U = (kMixPerThread + R - 1) / R;  // butterflies per thread at most
   const int BC = 1 << lbc;
   const int m = L / R;
-  const int tstep = L / (Ns * R);  // w_{Ns R} = tw[tstep]
-  for (int i = threadIdx.x; i < (m << lbc); i += kMixThreads) {
-    const int b = i & (BC - 1);
-    const int j = i >> lbc;
-    const int g = mag_ns ? (int)__umulhi((uint32_t)j, mag_ns) : j;  // j / Ns
-    const int k = j - g * Ns;
-    float2 v[R];
+  const int nb = m << lbc;            // butterflies of the block
+  const int tstep = L / (Ns * R);     // w_{Ns R} = tw[tstep]
+  float2 v[U][R];
+  int dst[U];
 #pragma unroll
-    for (int q = 0; q < R; ++q) v[q] = x[((j + q * m) << lbc) + b];
-    if (k != 0) {
-      const int e = tstep * k;
+  for (int u = 0; u < U; ++u) {
+    const int i = threadIdx.x + u * kMixThreads;
+    dst[u] = -1;
+    if (i < nb) {
+      const int b = i & (BC - 1);
+      const int j = i >> lbc;
+      const int g = mag_ns ? (int)__umulhi((uint32_t)j, mag_ns) : j;  // j / Ns
+      const int k = j - g * Ns;
 #pragma unroll
-      for (int q = 1; q < R; ++q) {
-        const int t = q * e;
-        v[q] = cmul(v[q], tw[t - L * (int)__umulhi((uint32_t)t, mag_l)]);  // (q e) mod L
+      for (int q = 0; q < R; ++q) v[u][q] = x[((j + q * m) << lbc) + b];
+      if (k != 0) {
+        const int e = tstep * k;
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          const int t = q * e;
+          v[u][q] = cmul(v[u][q], tw[t - L * (int)__umulhi((uint32_t)t, mag_l)]);  // (q e) mod L
+        }
       }
+      small_dft<R, SIGN>(v[u]);
+      dst[u] = ((g * Ns * R + k) << lbc) + b;
     }
-    small_dft<R, SIGN>(v);
-    const int base = g * Ns * R + k;
-#pragma unroll
-    for (int q = 0; q < R; ++q) y[((base + q * Ns) << lbc) + b] = v[q];
   }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (dst[u] >= 0) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) x[dst[u] + ((q * Ns) << lbc)] = v[u][q];
+    }
+  __syncthreads();
 }
 
 template <int SIGN>
 struct FftMixedBody {
   using Args = FftMixedArgs;
   static constexpr int kThreads = kMixThreads;
+  static constexpr int kMinWavesPerEU = 4;  // up to four blocks per CU (32 KiB of LDS each)
   static __device__ __forceinline__ void run(const FftMixedArgs& m, uint32_t blk, uint32_t) {
     extern __shared__ float2 lds[];
     const FftLines& a = m.f;
     const int L = a.L;
-    const int BC = 1 << m.lbc;
+    const int lbc = m.lbc;
+    const int BC = 1 << lbc;
+    const int ne = L << lbc;
     const int64_t nbc = (a.B + BC - 1) / BC;
     const int64_t o = blk / nbc;
     const int64_t bc = blk - o * nbc;
     float2* x = lds;
-    float2* y = lds + L * BC;
-    const float2* __restrict__ in = a.in + o * a.s_in_o + bc * BC;
-    for (int i = threadIdx.x; i < L * BC; i += kMixThreads) {
-      const int b = i & (BC - 1);
-      const int l = i >> m.lbc;
-      x[i] = bc * BC + b < a.B ? load_stream(&in[(int64_t)l * a.s_in_l + b]) : make_float2(0.f, 0.f);
+    {
+      const float2* __restrict__ in = a.in + o * a.s_in_o + bc * BC;
+      float2 t[kMixPerThread];
+#pragma unroll
+      for (int u = 0; u < kMixPerThread; ++u) {
+        const int i = threadIdx.x + u * kMixThreads;
+        const int b = i & (BC - 1);
+        t[u] = (i < ne && bc * BC + b < a.B) ? load_stream(&in[(int64_t)(i >> lbc) * a.s_in_l + b])
+                                             : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < kMixPerThread; ++u) {
+        const int i = threadIdx.x + u * kMixThreads;
+        if (i < ne) x[i] = t[u];
+      }
     }
     __syncthreads();
     int Ns = 1;
     for (int p = 0; p < m.npass; ++p) {
-      const int R = m.rad[p];
-      const uint32_t mg = m.mag_ns[p];
+      const int R = (int)((m.radices >> (4 * p)) & 15u);
+      const uint32_t mg = magic_div(Ns);
       if (R == 8)
-        stockham_pass<8, SIGN>(x, y, L, m.lbc, Ns, mg, m.mag_l, a.tw);
+        stockham_pass<8, SIGN>(x, L, lbc, Ns, mg, m.mag_l, a.tw);
       else if (R == 4)
-        stockham_pass<4, SIGN>(x, y, L, m.lbc, Ns, mg, m.mag_l, a.tw);
+        stockham_pass<4, SIGN>(x, L, lbc, Ns, mg, m.mag_l, a.tw);
       else if (R == 2)
-        stockham_pass<2, SIGN>(x, y, L, m.lbc, Ns, mg, m.mag_l, a.tw);
+        stockham_pass<2, SIGN>(x, L, lbc, Ns, mg, m.mag_l, a.tw);
       else if (R == 3)
-        stockham_pass<3, SIGN>(x, y, L, m.lbc, Ns, mg, m.mag_l, a.tw);
+        stockham_pass<3, SIGN>(x, L, lbc, Ns, mg, m.mag_l, a.tw);
       else
-        stockham_pass<5, SIGN>(x, y, L, m.lbc, Ns, mg, m.mag_l, a.tw);
-      __syncthreads();
-      float2* t = x;
-      x = y;
-      y = t;
+        stockham_pass<5, SIGN>(x, L, lbc, Ns, mg, m.mag_l, a.tw);
       Ns *= R;
     }
     float2* __restrict__ out = a.out + o * a.s_out_o + bc * BC;
     const int h = a.n_out / 2;
-    for (int i = threadIdx.x; i < L * BC; i += kMixThreads) {
+    for (int i = threadIdx.x; i < ne; i += kMixThreads) {
       const int b = i & (BC - 1);
-      const int k = i >> m.lbc;
+      const int k = i >> lbc;
       if (bc * BC + b >= a.B) continue;
       int P;
       if (a.centred == 1)
@@ -263,25 +295,21 @@ sar_status launch_mixed(const FftLines& a, LaunchSink& sink) {
   for (int r : {8, 4, 2, 3, 5})
     while (n % r == 0) {
       if (m.npass == kMixMaxPasses) return fail(SAR_ERR_UNSUPPORTED, "FFT length has too many factors");
-      m.rad[m.npass++] = r;
+      m.radices |= (uint64_t)r << (4 * m.npass++);
       n /= r;
     }
   if (n != 1) return fail(SAR_ERR_UNSUPPORTED, "FFT length not a product of 2, 3 and 5: " + std::to_string(a.L));
   if (a.L > kMixMaxElems) return fail(SAR_ERR_UNSUPPORTED, "FFT length too long: " + std::to_string(a.L));
+  // batch columns per block: up to 16 (128-byte row segments) while the
+  // block's lines fit its 32 KiB of LDS
   int bc = 1;
   while (bc < 16 && 2 * bc * a.L <= kMixMaxElems && bc < a.B) bc *= 2;
   while ((1 << m.lbc) < bc) ++m.lbc;
-  auto magic = [](int d) { return d <= 1 ? 0u : (uint32_t)(((1ull << 32) + (uint64_t)d - 1) / (uint64_t)d); };
-  int ns = 1;
-  for (int q = 0; q < m.npass; ++q) {
-    m.mag_ns[q] = magic(ns);
-    ns *= m.rad[q];
-  }
-  m.mag_l = magic(a.L);
+  m.mag_l = (uint32_t)(((1ull << 32) + (uint64_t)a.L - 1) / (uint64_t)a.L);
   const int64_t nblk = (a.B + bc - 1) / bc * a.n_outer;
   if (nblk <= 0) return SAR_OK;
   if (nblk > 0x7fffffffLL) return fail(SAR_ERR_UNSUPPORTED, "FFT batch too large");
-  const size_t lds = 2 * (size_t)a.L * bc * sizeof(float2);
+  const size_t lds = (size_t)a.L * bc * sizeof(float2);
   if (a.sign < 0) return launch_body<FftMixedBody<-1>>(sink, (uint32_t)nblk, lds, m, "fft launch");
   return launch_body<FftMixedBody<+1>>(sink, (uint32_t)nblk, lds, m, "fft launch");
 }

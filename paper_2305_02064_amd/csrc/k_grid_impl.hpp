@@ -509,7 +509,11 @@ sar_status grid_w(const Plan& p, const void* d_echo, float echo_scale, const Wor
 }
 
 }  // namespace grid_impl
+}  // namespace sar
 
+#include "k_grid_union.hpp"
+
+namespace sar {
 // Each tile configuration is compiled for the kernel widths of
 // kGridTileWidths; the plan only selects a compiled one.
 #define SAR_INSTANTIATE_GRID(W)                                                                    \
@@ -520,6 +524,9 @@ sar_status grid_w(const Plan& p, const void* d_echo, float echo_scale, const Wor
     }                                                                                              \
     if constexpr ((W) >= kGridTileWidths[2][0] && (W) <= kGridTileWidths[2][1]) {                  \
       if (p.grid_tile == 2) return grid_impl::grid_w<W, 2>(p, d_echo, echo_scale, ws, grid, sink);  \
+    }                                                                                              \
+    if constexpr ((W) >= kGridTileWidths[3][0] && (W) <= kGridTileWidths[3][1]) {                  \
+      if (p.grid_tile == 3) return grid_impl::grid_union_w<W>(p, d_echo, echo_scale, ws, grid, sink); \
     }                                                                                              \
     return grid_impl::grid_w<W, 0>(p, d_echo, echo_scale, ws, grid, sink);                        \
   }

@@ -1,0 +1,385 @@
+// Steps a1 + a2, multi-wave form (included by k_grid_impl.hpp): compensation
+// (Eq. (11)) and Kaiser-Bessel gridding with each compensated echo value
+// shared by the four waves of a workgroup.
+//
+// A workgroup owns a union of 8 x 8 grid cells for 128 frequencies (two per
+// lane).  Wave w owns the union's rows w and w + 4, all 8 columns: 2 x 8 x 2
+// complex accumulators per lane.  Every sample whose W x W support (W <= 4)
+// touches the union covers W consecutive rows, so it lands in at most one row
+// of each wave and every wave visits nearly every sample once: the waves stay
+// in step.  The union's samples (rows of first-tap cells, contiguous runs of
+// the cell-sorted list) stream through LDS in chunks of 16: the four waves
+// stage a chunk's echo rows and kernel weights with gfx950's direct
+// global-to-LDS loads, then each compensates a quarter of the chunk in place
+// (float64 argument k * beta reduced modulo one cycle, hardware sine and
+// cosine) and the workgroup forms each sample's W x W weight products once;
+// after a barrier every wave walks the chunk, adding one product row times
+// the values into its accumulators through a fully unrolled body per tap
+// pattern.  Compared with one wave per 4 x 4 tile, a sample is compensated
+// 1.9 instead of 3.1 times on average, and a visit does no per-row scaling.
+// Rows of cells partition the grid: each value is written once with streaming
+// stores, no atomics, a fixed summation order.
+#pragma once
+
+namespace sar {
+namespace grid_impl {
+
+constexpr int kUnionWaves = 4;
+constexpr int kUnionX = 8;     // cells along x per union
+constexpr int kUnionY = 8;     // rows per union (two per wave, four apart)
+constexpr int kUnionCh = 16;   // samples per chunk
+
+// whether pattern I (see pattern_of) puts a tap row on one of the wave's rows
+template <int W, int NBX, int NWV, int RPW>
+constexpr bool union_has_tap(int I) {
+  const int fr = I / NBX - (NWV - 1) - (W - 1);
+  const int r0 = fr <= 0 ? 0 : (fr + NWV - 1) / NWV;
+  return r0 < RPW && NWV * r0 - fr < W;
+}
+
+template <int W, int ET>
+struct GridUnionBody {
+  using Args = GridArgs;
+  static constexpr int kThreads = 64 * kUnionWaves;
+  static constexpr int kMinWavesPerEU = 4;
+  static __device__ __forceinline__ void run(const GridArgs& a, uint32_t blk, uint32_t nblk);
+};
+
+template <int W, int ET>
+__device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uint32_t blk, uint32_t nblk) {
+  static_assert(W >= 2 && W <= 4, "one product row of four weights per wave and sample");
+  constexpr int NWV = kUnionWaves;
+  constexpr int UX = kUnionX;
+  constexpr int UY = kUnionY;
+  constexpr int RPW = UY / NWV;       // rows per wave
+  constexpr int FPL = 2;              // frequencies per lane
+  constexpr int CH = kUnionCh;
+  constexpr int NBX = UX + W - 1;     // last-tap column offsets touching the union
+  constexpr int NBY = UY + W - 1;     // last-tap row offsets touching the union
+  constexpr int NA = NBY + NWV - 1;   // row offsets relative to a wave's first row
+  constexpr int NSEG = 2 * NBY;       // each row of cells may split at the x wrap
+  constexpr int EB = FPL * 512;       // bytes of one sample's compensated values
+  constexpr int NW = 2 * W;           // weight words per sample (wx then wy)
+  constexpr int WS = (NW + 3) / 4 * 4;
+  constexpr int VOFF = 0;
+  constexpr int WOFF = CH * EB;                 // raw weights (direct loads)
+  constexpr int POFF = WOFF + CH * WS * 4;      // products [CH][4 rows][4]
+  constexpr int BUF = POFF + CH * 64;
+  static_assert(NA * NBX <= 256, "pattern chain covers 256 patterns");
+  static_assert(CH * WS <= 128, "weights of a chunk in two direct loads");
+  static_assert(CH * 16 == 64 * NWV, "one product per thread and chunk");
+  __shared__ int seg_s[NSEG];
+  __shared__ int seg_off[NSEG + 1];
+  __shared__ __attribute__((aligned(16))) char cbuf[2][BUF];
+
+  const uint32_t work = xcd_remap(blk, nblk);
+  const int nux = a.ntx;  // unions along x (mx / 8)
+  const int nuy = a.nty;
+  const int ux = (int)(work % (uint32_t)nux);
+  const uint32_t rest = work / (uint32_t)nux;
+  const int uy = (int)(rest % (uint32_t)nuy);
+  const int fchunk = (int)(rest / (uint32_t)nuy);
+  const int ux0 = ux * UX, uy0 = uy * UY;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int fbase = fchunk * 64 * FPL;
+  int fq[FPL];
+  double fcc[FPL];
+#pragma unroll
+  for (int h = 0; h < FPL; ++h) {
+    fq[h] = fbase + 64 * h + lane;
+    fcc[h] = a.fcc[fq[h] < a.nf ? fq[h] : a.nf - 1];
+  }
+  // runs of first-tap cells: row j (y offset j - (W-1)), x in [ux0 - (W-1), ux0 + UX)
+  if (threadIdx.x < NBY) {
+    const int j = threadIdx.x;
+    int cy = uy0 + j - (W - 1);
+    cy = cy < 0 ? cy + a.my : cy;
+    const int64_t row = (int64_t)cy * a.mx;
+    const int xlo = ux0 - (W - 1);
+    const int xhi = ux0 + UX;
+    int s0, e0, s1 = 0, e1 = 0;
+    if (xlo >= 0) {
+      s0 = a.cell_start[row + xlo];
+      e0 = a.cell_start[row + xhi];
+    } else {
+      s0 = a.cell_start[row + a.mx + xlo];
+      e0 = a.cell_start[row + a.mx];
+      s1 = a.cell_start[row];
+      e1 = a.cell_start[row + xhi];
+    }
+    seg_s[2 * j] = s0;
+    seg_s[2 * j + 1] = s1;
+    seg_off[2 * j] = e0 - s0;
+    seg_off[2 * j + 1] = e1 - s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int k = 0; k < NSEG; ++k) {
+      const int l = seg_off[k];
+      seg_off[k] = run;
+      run += l;
+    }
+    seg_off[NSEG] = run;
+  }
+  __syncthreads();
+  const int total = __builtin_amdgcn_readfirstlane(seg_off[NSEG]);
+  const int nchunk = (total + CH - 1) / CH;
+
+  // sorted-list index of the chunk's lane-th sample (lanes >= CH or past the
+  // end: -1); chunks are asked for in increasing order, so each lane keeps
+  // the segment it reached last time
+  int kseg = 0;
+  auto chunk_index = [&](int c) __attribute__((always_inline)) -> int {
+    const int t = c * CH + lane;
+    if (lane >= CH || t >= total) return -1;
+    while (seg_off[kseg + 1] <= t) ++kseg;
+    return seg_s[kseg] + (t - seg_off[kseg]);
+  };
+  const SampleRec<W>* __restrict__ grec = (const SampleRec<W>*)a.rec;
+  auto gather_beta = [&](int sidx) __attribute__((always_inline)) -> double {
+    return sidx >= 0 ? grec[sidx].beta : 0.0;
+  };
+  // last-tap cell gathered a chunk ahead, turned into the pattern only when
+  // the chunk is processed (a use at once would wait for all earlier loads)
+  auto gather_cxy = [&](int sidx) __attribute__((always_inline)) -> uint32_t {
+    return sidx >= 0 ? *(const uint32_t*)&grec[sidx].cx : 0u;
+  };
+  // pattern of a sample for this wave: (last-tap row relative to the wave's
+  // first row, shifted to >= 0) x NBX + last-tap column relative to the
+  // union, or -1 when none of the wave's rows is among the sample's tap rows
+  // (such samples are skipped, not walked through empty bodies)
+  auto pattern_of = [&](uint32_t cxy) __attribute__((always_inline)) -> int {
+    int aa = (int)(cxy >> 16) - uy0;
+    int bb = (int)(cxy & 0xffffu) - ux0;
+    aa += aa < 0 ? a.my : 0;
+    bb += bb < 0 ? a.mx : 0;
+    const int fr = aa - wv - (W - 1);                        // first tap row from the wave's first row
+    const int r0 = fr <= 0 ? 0 : (fr + NWV - 1) / NWV;       // the wave's first row at or after it
+    const bool tap = r0 < RPW && NWV * r0 - fr < W;
+    return tap ? (aa - wv + NWV - 1) * NBX + bb : -1;
+  };
+  constexpr int RF = (int)(sizeof(SampleRec<W>) / 4);
+  constexpr int WREC = (int)(offsetof(SampleRec<W>, wx) / 4);
+  const bool quad_ok = (a.nf & 1) == 0;
+  // chunk c into buffer b: wave wv stages the echo rows of samples
+  // k = wv, wv + 4, ... and waves 0 and 1 the kernel weights
+  auto stage = [&](int c, int b, int srcv, int sidxv) __attribute__((always_inline)) {
+    const int n = min(CH, total - c * CH);
+    char* buf = cbuf[b];
+    for (int k = wv; k < n; k += NWV) {
+      const int src = __builtin_amdgcn_readlane(srcv, k);
+      if constexpr (ET != SAR_ECHO_F16X2) {
+        const float* row = (const float*)a.echo + (int64_t)src * a.nf * 2;
+        if (quad_ok) {
+          const int fi = fbase * 2 + 4 * lane;
+          dma_quad(row + (fi < 2 * a.nf ? fi : 0), buf + VOFF + k * EB);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2 * FPL; ++q) {
+            const int fi = fbase * 2 + q * 64 + lane;
+            dma_dword(row + (fi < 2 * a.nf ? fi : 0), buf + VOFF + k * EB + q * 256);
+          }
+        }
+      } else {
+        const uint32_t* row = (const uint32_t*)a.echo + (int64_t)src * a.nf;
+#pragma unroll
+        for (int q = 0; q < FPL; ++q) {
+          const int fi = fbase + q * 64 + lane;
+          dma_dword(row + (fi < a.nf ? fi : 0), buf + VOFF + k * EB + q * 256);
+        }
+      }
+    }
+    if (wv < (CH * WS + 63) / 64) {
+      const int L = wv * 64 + lane;
+      const int k = L / WS;
+      const int wd = L - k * WS;
+      const int si = __shfl(sidxv, k < n ? k : 0);
+      const float* src = (const float*)a.rec + (int64_t)si * RF + WREC + (wd < NW ? wd : 0);
+      dma_dword(src, buf + WOFF + wv * 256);
+    }
+  };
+
+  float2 acc[RPW][UX][FPL];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < UX; ++c)
+#pragma unroll
+      for (int h = 0; h < FPL; ++h) acc[r][c][h] = make_float2(0.f, 0.f);
+
+  int sidx0 = chunk_index(0);
+  int sidx1 = chunk_index(1);
+  double beta0 = gather_beta(sidx0);
+  uint32_t cxy0 = gather_cxy(sidx0);
+  int src1 = sidx1 >= 0 ? a.order[sidx1] : 0;
+  if (nchunk > 0) stage(0, 0, sidx0 >= 0 ? a.order[sidx0] : 0, sidx0);
+  for (int c = 0; c < nchunk; ++c) {
+    char* buf = cbuf[c & 1];
+    // the chunk's direct loads (every wave's) have landed, and every wave is
+    // done with the buffer the next stage overwrites
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int n = __builtin_amdgcn_readfirstlane(min(CH, total - c * CH));
+    const int idx0 = pattern_of(cxy0);
+    // compensation of this wave's quarter of the chunk, in place:
+    // s_hat = s exp(+j 2 pi f beta / c), float64 argument reduced mod a cycle
+    for (int k = wv; k < n; k += NWV) {
+      const double bk = readlane_f64(beta0, k);
+      float2 t2[FPL];
+#pragma unroll
+      for (int h = 0; h < FPL; ++h) {
+        if constexpr (ET != SAR_ECHO_F16X2) {
+          t2[h] = *(const float2*)(buf + VOFF + k * EB + h * 512 + lane * 8);
+        } else {
+          const float2 w2 = __half22float2(*(const __half2*)(buf + VOFF + k * EB + h * 256 + lane * 4));
+          t2[h] = make_float2(w2.x * a.echo_scale, w2.y * a.echo_scale);
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < FPL; ++h) {
+        if constexpr (ET == kEchoC64Fp32Args)
+          *(float2*)(buf + VOFF + k * EB + h * 512 + lane * 8) =
+              cmul(t2[h], cis_cycles_f32((float)bk * (float)fcc[h]));
+        else
+          *(float2*)(buf + VOFF + k * EB + h * 512 + lane * 8) = cmul(t2[h], cis_cycles(bk * fcc[h]));
+      }
+    }
+    // weight products: thread t forms product (jj, kk) of sample t / 16
+    {
+      const int t = threadIdx.x;
+      const int k = t >> 4;
+      const int jj = (t >> 2) & 3;
+      const int kk = t & 3;
+      float pr = 0.f;
+      if (k < n && jj < W && kk < W) {
+        const float* wk = (const float*)(buf + WOFF) + k * WS;
+        pr = wk[kk] * wk[W + jj];
+      }
+      ((float*)(buf + POFF))[t] = pr;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (c + 1 < nchunk) stage(c + 1, (c + 1) & 1, src1, sidx1);
+    const int sidx2 = chunk_index(c + 2);
+    const int src2 = sidx2 >= 0 ? a.order[sidx2] : 0;
+    const double beta1 = gather_beta(sidx1);
+    const uint32_t cxy1 = gather_cxy(sidx1);
+    int k = 0;
+    typedef __attribute__((address_space(3))) char lds_char;
+    const uint32_t vbase = (uint32_t)(uintptr_t)(lds_char*)buf + (uint32_t)(VOFF + 8 * lane);
+    const uint32_t pbase = (uint32_t)(uintptr_t)(lds_char*)(buf + POFF);
+    // one sample with its tap pattern fixed at compile time: I = (row offset
+    // of its last tap from this wave's first row + NWV - 1) * NBX + column
+    // offset of its last tap from the union
+    auto visit = [&](auto ic) __attribute__((always_inline)) {
+      constexpr int I = decltype(ic)::value;
+      constexpr int AP = I / NBX - (NWV - 1);   // last-tap row offset from the wave's first row
+      constexpr int BB = I % NBX;               // last-tap column offset
+      constexpr int FR = AP - (W - 1);          // first-tap row offset
+      // the wave's row r (offset 4 r) takes tap row 4 r - FR if that is in [0, W)
+      constexpr int R0 = (FR <= 0) ? 0 : (FR + NWV - 1) / NWV;
+      constexpr int JJ = NWV * R0 - FR;
+      if constexpr (R0 < RPW && JJ >= 0 && JJ < W) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        f2v r0, r1;
+        f4v q;
+        const uint32_t va = vbase + (uint32_t)(k * EB);
+        const uint32_t pa = pbase + (uint32_t)(k * 64);
+        asm volatile(
+            "ds_read_b64 %0, %3\n\tds_read_b64 %1, %3 offset:512\n\t"
+            "ds_read_b128 %2, %4 offset:%5\n\ts_waitcnt lgkmcnt(0)"
+            : "=&v"(r0), "=&v"(r1), "=&v"(q)
+            : "v"(va), "v"(pa), "i"(JJ * 16)
+            : "memory");
+        const float wp[4] = {q.x, q.y, q.z, q.w};
+        const float2 v[FPL] = {make_float2(r0.x, r0.y), make_float2(r1.x, r1.y)};
+        static_for<0, W>([&](auto kc) __attribute__((always_inline)) {
+          constexpr int kk = decltype(kc)::value;
+          constexpr int cc = BB - (W - 1) + kk;
+          if constexpr (cc >= 0 && cc < UX) {
+#pragma unroll
+            for (int h = 0; h < FPL; ++h) cfma(acc[R0][cc][h], v[h], wp[kk]);
+          }
+        });
+      }
+    };
+    int cur = __builtin_amdgcn_readlane(idx0, 0);
+    for (;;) {
+      switch (cur) {
+#define SAR_UNION_CASE(I)                                                  \
+  case (I):                                                                \
+    if constexpr ((I) < NA * NBX && union_has_tap<W, NBX, NWV, RPW>(I)) {  \
+      while (cur == (I)) {                                                 \
+        visit(std::integral_constant<int, (I)>{});                         \
+        if (++k >= n) goto chunk_done;                                     \
+        cur = __builtin_amdgcn_readlane(idx0, k);                          \
+      }                                                                    \
+    }                                                                      \
+    [[fallthrough]];
+        SAR_GRID_CASES(SAR_UNION_CASE)
+#undef SAR_UNION_CASE
+        default:
+          break;
+      }
+      if (cur < 0 || cur >= NA * NBX) {
+        if (++k >= n) break;
+        cur = __builtin_amdgcn_readlane(idx0, k);
+      }
+    }
+  chunk_done:
+    sidx0 = sidx1;
+    sidx1 = sidx2;
+    src1 = src2;
+    beta0 = beta1;
+    cxy0 = cxy1;
+  }
+
+  // the store addresses are formed only here: an opaque lane offset keeps the
+  // compiler from hoisting 32 of them, live across the whole chunk loop
+  int off = lane;
+  asm volatile("" : "+v"(off));
+#pragma unroll
+  for (int h = 0; h < FPL; ++h) {
+    if (fbase + 64 * h + off < a.nf) {
+      float2* g = a.grid + ((int64_t)(uy0 + wv) * a.mx + ux0) * a.nf + fbase + 64 * h + off;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int c = 0; c < UX; ++c) store_stream(g + ((int64_t)NWV * r * a.mx + c) * a.nf, acc[r][c][h]);
+    }
+  }
+}
+
+template <int W>
+sar_status grid_union_w(const Plan& p, const void* d_echo, float echo_scale, const Workspace& ws, float2* grid,
+                        LaunchSink& sink) {
+  GridArgs a;
+  a.rec = ws.rec;
+  a.cell_start = ws.cell_start;
+  a.order = ws.order;
+  a.echo = d_echo;
+  a.echo_scale = echo_scale;
+  a.fcc = p.d_fcc;
+  a.grid = grid;
+  a.mx = p.mx;
+  a.my = p.my;
+  a.nf = p.nf;
+  a.ntx = p.mx / kUnionX;
+  a.nty = p.my / kUnionY;
+  const int nfc = (p.nf + 127) / 128;
+  const int64_t nblk = (int64_t)a.ntx * a.nty * nfc;
+  if (p.flags & SAR_FP32_ARGS) {
+    if constexpr (W == 4)
+      return launch_body<GridUnionBody<W, kEchoC64Fp32Args>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
+    return fail(SAR_ERR_UNSUPPORTED, "SAR_FP32_ARGS is compiled for a 4-tap lateral kernel");
+  }
+  if (p.echo_type == SAR_ECHO_C64)
+    return launch_body<GridUnionBody<W, SAR_ECHO_C64>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
+  return launch_body<GridUnionBody<W, SAR_ECHO_F16X2>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
+}
+
+}  // namespace grid_impl
+}  // namespace sar

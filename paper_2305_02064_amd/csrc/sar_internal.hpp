@@ -15,9 +15,11 @@ namespace sar {
 constexpr int kNumStages = 7;
 // gridding tile configurations: cells along x, along y, frequencies per lane,
 // and the kernel widths each is compiled for
-constexpr int kNumGridTiles = 3;
-constexpr int kGridTiles[kNumGridTiles][3] = {{4, 4, 2}, {8, 8, 1}, {8, 4, 2}};
-constexpr int kGridTileWidths[kNumGridTiles][2] = {{3, 8}, {3, 5}, {5, 6}};  // none spills registers
+// (configuration 3: a four-wave workgroup over 8 x 8 cells sharing each
+// compensated value, a wave per pair of rows four apart)
+constexpr int kNumGridTiles = 4;
+constexpr int kGridTiles[kNumGridTiles][3] = {{4, 4, 2}, {8, 8, 1}, {8, 4, 2}, {8, 8, 2}};
+constexpr int kGridTileWidths[kNumGridTiles][2] = {{3, 8}, {3, 5}, {5, 6}, {3, 4}};  // none spills registers
 constexpr bool grid_tile_compiled(int tile, int w) {
   return tile >= 0 && tile < kNumGridTiles && w >= kGridTileWidths[tile][0] && w <= kGridTileWidths[tile][1];
 }

@@ -341,9 +341,9 @@ def test_stolt_grid_sizes(torch_cuda, nz):
 @pytest.mark.parametrize("width,nf", [(4, 40), (4, 200), (5, 40), (5, 200), (6, 200)])
 def test_gridding_tiles_agree(torch_cuda, width, nf):
     # every tile configuration compiled for the width (4x4 cells, 2
-    # frequencies per lane; 8x8 cells, 1 frequency; 8x4 cells, 2 frequencies)
-    # against each other and the oracle; 200 frequencies leave a ragged last
-    # frequency chunk
+    # frequencies per lane; 8x8 cells, 1 frequency; 8x4 cells, 2 frequencies;
+    # the four-wave 8x8 union, 2 frequencies) against each other and the
+    # oracle; 200 frequencies leave a ragged last frequency chunk
     grid = ImageGrid(nx=16, ny=32, nz=8, x0=-0.008, y0=-0.015, z0=0.25, dx=1e-3, dy=0.95e-3, dz=0.01,
                      z_ref=0.0, z_focus=0.3)
     scan = _ragged_scan(70 + width + nf, 211, nf, grid)
@@ -352,7 +352,7 @@ def test_gridding_tiles_agree(torch_cuda, width, nf):
     pos, echo, _ = to_device(scan)
     from paper_2305_02064_amd import sar
     tiles, specs = [], []
-    for tile in (0, 1, 2):
+    for tile in (0, 1, 2, 3):
         try:
             plan.set_grid_tile(tile)
         except sar.SarError as e:   # not compiled for this width
@@ -376,7 +376,7 @@ def test_autotune_keeps_a_working_tile(torch_cuda, tiny):
     plan = make_plan(scan)
     pos, echo, _ = to_device(scan)
     tile = plan.autotune(pos, echo)
-    assert tile in (0, 1, 2) and plan.info["grid_tile"] == tile
+    assert tile in (0, 1, 2, 3) and plan.info["grid_tile"] == tile
     img = plan.reconstruct(pos, echo).cpu().numpy()
     assert rel_l2(img, img_ref) <= IMAGE_TOL
     plan.set_grid_tile(tile)
