@@ -100,11 +100,13 @@ struct ZeroBody {
   struct Args {
     int32_t* p;
     int64_t n;
+    int32_t* one;  // one more word to clear (may be null)
   };
   static constexpr int kThreads = 256;
   static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
     const int64_t i = (int64_t)b * kThreads + threadIdx.x;
     if (i < a.n) a.p[i] = 0;
+    if (i == 0 && a.one) *a.one = 0;
   }
 };
 
@@ -446,7 +448,8 @@ sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, in
   }
   sar_status st;
   const char* what = "geometry/sort launch";
-  if ((st = launch_body<ZeroBody>(sink, blocks_for(ncell + 1, 256), 0, {ws.cell_start, ncell + 1}, what)) != SAR_OK)
+  if ((st = launch_body<ZeroBody>(sink, blocks_for(ncell + 1, 256), 0, {ws.cell_start, ncell + 1, ws.split_count},
+                                  what)) != SAR_OK)
     return st;
   if ((st = launch_body<KeysBody<W>>(sink, blocks_for(n_v_grid, 256), 0, {g, ws.key, ws.cell_start}, what)) !=
       SAR_OK)

@@ -93,6 +93,15 @@ struct GridArgs {
   float2* grid;       // [my][mx][nf]
   int mx, my, nf;
   int ntx, nty;
+  // over-full unions (four-wave kernel only): per union the first overflow
+  // slot (-1: not split), the slot list (union, part), partial grids per slot
+  const int32_t* uofs;
+  const int2* slots;
+  float2* partial;    // [slot][64 cells][nf]
+  const int32_t* nslots_used;
+  int max_slots;
+  int part_len;       // samples of a union's stream per part
+  int nmain;          // blocks of the union grid (the rest take overflow slots)
 };
 
 // value of lane k of a float64 register pair

@@ -19,6 +19,14 @@
 // 1.9 instead of 3.1 times on average, and a visit does no per-row scaling.
 // Rows of cells partition the grid: each value is written once with streaming
 // stores, no atomics, a fixed summation order.
+//
+// Irregular density: a union whose sample stream is longer than a part
+// (a dwelling hand piles thousands of samples into a few cells) is split.  A
+// planning kernel takes ceil(length / part) - 1 overflow slots for it; the
+// union's own workgroup walks the first part and writes the grid, extra
+// workgroups (one per slot and frequency chunk) walk the later parts into
+// partial grids, and a combining kernel adds the partials in part order.  The
+// sum is therefore the same on every run, whichever slots a union gets.
 #pragma once
 
 namespace sar {
@@ -72,13 +80,29 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
   __shared__ int seg_off[NSEG + 1];
   __shared__ __attribute__((aligned(16))) char cbuf[2][BUF];
 
-  const uint32_t work = xcd_remap(blk, nblk);
   const int nux = a.ntx;  // unions along x (mx / 8)
   const int nuy = a.nty;
-  const int ux = (int)(work % (uint32_t)nux);
-  const uint32_t rest = work / (uint32_t)nux;
-  const int uy = (int)(rest % (uint32_t)nuy);
-  const int fchunk = (int)(rest / (uint32_t)nuy);
+  int ux, uy, fchunk, slot = -1, part = 0;
+  if ((int)blk < a.nmain) {
+    const uint32_t work = xcd_remap(blk, (uint32_t)a.nmain);
+    ux = (int)(work % (uint32_t)nux);
+    const uint32_t rest = work / (uint32_t)nux;
+    uy = (int)(rest % (uint32_t)nuy);
+    fchunk = (int)(rest / (uint32_t)nuy);
+  } else {
+    // an overflow slot: a later part of a split union
+    const int nfc = a.nmain / (nux * nuy);
+    const int o = (int)blk - a.nmain;
+    slot = o / nfc;
+    fchunk = o - slot * nfc;
+    const int used = min(*a.nslots_used, a.max_slots);
+    if (slot >= used) return;
+    const int2 e = a.slots[slot];
+    if (e.x < 0) return;
+    ux = e.x % nux;
+    uy = e.x / nux;
+    part = e.y & 0xffff;
+  }
   const int ux0 = ux * UX, uy0 = uy * UY;
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -124,7 +148,17 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
     seg_off[NSEG] = run;
   }
   __syncthreads();
-  const int total = __builtin_amdgcn_readfirstlane(seg_off[NSEG]);
+  const int total_all = __builtin_amdgcn_readfirstlane(seg_off[NSEG]);
+  // stream positions [t0, t1) of this block: the whole union, its first part
+  // (split union), or a later part (overflow slot)
+  int t0 = 0, t1 = total_all;
+  if (slot >= 0) {
+    t0 = part * a.part_len;
+    t1 = min(total_all, t0 + a.part_len);
+  } else if (a.max_slots > 0 && a.uofs[uy * nux + ux] >= 0) {
+    t1 = min(total_all, a.part_len);
+  }
+  const int total = t1 - t0;
   const int nchunk = (total + CH - 1) / CH;
 
   // sorted-list index of the chunk's lane-th sample (lanes >= CH or past the
@@ -132,8 +166,8 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
   // the segment it reached last time
   int kseg = 0;
   auto chunk_index = [&](int c) __attribute__((always_inline)) -> int {
-    const int t = c * CH + lane;
-    if (lane >= CH || t >= total) return -1;
+    const int t = t0 + c * CH + lane;
+    if (lane >= CH || t >= t1) return -1;
     while (seg_off[kseg + 1] <= t) ++kseg;
     return seg_s[kseg] + (t - seg_off[kseg]);
   };
@@ -341,16 +375,113 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
   // compiler from hoisting 32 of them, live across the whole chunk loop
   int off = lane;
   asm volatile("" : "+v"(off));
+  // the grid (cell rows mx apart) or the slot's partial grid (rows UX apart)
+  float2* gbase;
+  int64_t rstride;
+  if (slot < 0) {
+    gbase = a.grid + ((int64_t)(uy0 + wv) * a.mx + ux0) * a.nf;
+    rstride = (int64_t)a.mx * a.nf;
+  } else {
+    gbase = a.partial + ((int64_t)slot * UX * UY + wv * UX) * a.nf;
+    rstride = (int64_t)UX * a.nf;
+  }
 #pragma unroll
   for (int h = 0; h < FPL; ++h) {
     if (fbase + 64 * h + off < a.nf) {
-      float2* g = a.grid + ((int64_t)(uy0 + wv) * a.mx + ux0) * a.nf + fbase + 64 * h + off;
+      float2* g = gbase + fbase + 64 * h + off;
 #pragma unroll
       for (int r = 0; r < RPW; ++r)
 #pragma unroll
-        for (int c = 0; c < UX; ++c) store_stream(g + ((int64_t)NWV * r * a.mx + c) * a.nf, acc[r][c][h]);
+        for (int c = 0; c < UX; ++c) store_stream(g + NWV * r * rstride + (int64_t)c * a.nf, acc[r][c][h]);
     }
   }
+}
+
+// Split planning: one thread per union counts its stream (the samples whose
+// first-tap cell lies in [x0 - (W-1), x0 + 8) x [y0 - (W-1), y0 + 8)) and takes
+// ceil(count / part) - 1 consecutive overflow slots; a union whose slots would
+// pass the end of the slot table runs unsplit (its slots are marked unused).
+// A slot holds (union, part | parts << 16).
+template <int W>
+struct UnionPlanBody {
+  struct Args {
+    const int32_t* cell_start;
+    int mx, my, nux, nuy;
+    int part_len, max_slots;
+    int32_t* counter;
+    int32_t* uofs;
+    int2* slots;
+  };
+  static constexpr int kThreads = 256;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
+    const int u = (int)b * kThreads + threadIdx.x;
+    if (u >= a.nux * a.nuy) return;
+    const int x0 = (u % a.nux) * kUnionX, y0 = (u / a.nux) * kUnionY;
+    int n = 0;
+    for (int j = 0; j < kUnionY + W - 1; ++j) {
+      int cy = y0 + j - (W - 1);
+      cy = cy < 0 ? cy + a.my : cy;
+      const int64_t row = (int64_t)cy * a.mx;
+      const int xlo = x0 - (W - 1), xhi = x0 + kUnionX;
+      if (xlo >= 0)
+        n += a.cell_start[row + xhi] - a.cell_start[row + xlo];
+      else
+        n += a.cell_start[row + a.mx] - a.cell_start[row + a.mx + xlo] + a.cell_start[row + xhi] -
+             a.cell_start[row];
+    }
+    const int extra = (n + a.part_len - 1) / a.part_len - 1;
+    if (extra <= 0) {
+      a.uofs[u] = -1;
+      return;
+    }
+    const int ofs = atomicAdd(a.counter, extra);
+    const bool fits = ofs + extra <= a.max_slots;
+    a.uofs[u] = fits ? ofs : -1;
+    for (int q = 0; q < extra && ofs + q < a.max_slots; ++q)
+      a.slots[ofs + q] = fits ? make_int2(u, (q + 1) | (extra << 16)) : make_int2(-1, 0);
+  }
+};
+
+// Adds the partial grids of a split union to the grid, in part order: the
+// block of the union's first overflow slot does it for all 64 cells.
+struct UnionCombineBody {
+  struct Args {
+    const int2* slots;
+    const int32_t* counter;
+    const float2* partial;
+    float2* grid;
+    int mx, nf, nux, max_slots;
+  };
+  static constexpr int kThreads = 256;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
+    const int s0 = (int)b;
+    if (s0 >= min(*a.counter, a.max_slots)) return;
+    const int2 e = a.slots[s0];
+    if (e.x < 0 || (e.y & 0xffff) != 1) return;
+    const int parts = e.y >> 16;
+    const int x0 = (e.x % a.nux) * kUnionX, y0 = (e.x / a.nux) * kUnionY;
+    const int per = kUnionX * kUnionY * a.nf;
+    for (int i = threadIdx.x; i < per; i += kThreads) {
+      const int cell = i / a.nf;
+      const int f = i - cell * a.nf;
+      float2* g = a.grid + ((int64_t)(y0 + cell / kUnionX) * a.mx + x0 + cell % kUnionX) * a.nf + f;
+      float2 v = *g;
+      for (int q = 0; q < parts; ++q) v = cadd(v, a.partial[(int64_t)(s0 + q) * per + i]);
+      *g = v;
+    }
+  }
+};
+
+template <int W>
+sar_status grid_union_launch(const Plan& p, const GridArgs& a, int64_t nblk, LaunchSink& sink) {
+  if (p.flags & SAR_FP32_ARGS) {
+    if constexpr (W == 4)
+      return launch_body<GridUnionBody<W, kEchoC64Fp32Args>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
+    return fail(SAR_ERR_UNSUPPORTED, "SAR_FP32_ARGS is compiled for a 4-tap lateral kernel");
+  }
+  if (p.echo_type == SAR_ECHO_C64)
+    return launch_body<GridUnionBody<W, SAR_ECHO_C64>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
+  return launch_body<GridUnionBody<W, SAR_ECHO_F16X2>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
 }
 
 template <int W>
@@ -370,15 +501,25 @@ sar_status grid_union_w(const Plan& p, const void* d_echo, float echo_scale, con
   a.ntx = p.mx / kUnionX;
   a.nty = p.my / kUnionY;
   const int nfc = (p.nf + 127) / 128;
-  const int64_t nblk = (int64_t)a.ntx * a.nty * nfc;
-  if (p.flags & SAR_FP32_ARGS) {
-    if constexpr (W == 4)
-      return launch_body<GridUnionBody<W, kEchoC64Fp32Args>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
-    return fail(SAR_ERR_UNSUPPORTED, "SAR_FP32_ARGS is compiled for a 4-tap lateral kernel");
+  const int nunion = a.ntx * a.nty;
+  a.uofs = ws.uofs;
+  a.slots = (const int2*)ws.slots;
+  a.partial = ws.partial;
+  a.nslots_used = ws.split_count;
+  a.max_slots = ws.max_slots;
+  a.part_len = kUnionPartLen;
+  a.nmain = nunion * nfc;
+  const int64_t nblk = (int64_t)a.nmain + (int64_t)a.max_slots * nfc;
+  if (a.max_slots > 0) {
+    typename UnionPlanBody<W>::Args pa{ws.cell_start, p.mx, p.my, a.ntx, a.nty, kUnionPartLen, a.max_slots,
+                                       ws.split_count, ws.uofs, (int2*)ws.slots};
+    sar_status st = launch_body<UnionPlanBody<W>>(sink, (uint32_t)((nunion + 255) / 256), 0, pa, "gridding launch");
+    if (st != SAR_OK) return st;
   }
-  if (p.echo_type == SAR_ECHO_C64)
-    return launch_body<GridUnionBody<W, SAR_ECHO_C64>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
-  return launch_body<GridUnionBody<W, SAR_ECHO_F16X2>>(sink, (uint32_t)nblk, 0, a, "gridding launch");
+  sar_status st = grid_union_launch<W>(p, a, nblk, sink);
+  if (st != SAR_OK || a.max_slots == 0) return st;
+  UnionCombineBody::Args ca{(const int2*)ws.slots, ws.split_count, ws.partial, grid, p.mx, p.nf, a.ntx, a.max_slots};
+  return launch_body<UnionCombineBody>(sink, (uint32_t)a.max_slots, 0, ca, "gridding launch");
 }
 
 }  // namespace grid_impl

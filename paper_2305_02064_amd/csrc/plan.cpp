@@ -496,6 +496,15 @@ size_t workspace_bytes(const Plan& p, int64_t n_pos, Workspace* ws, char* base) 
   const size_t o_order2 = take((size_t)n_v * 4);
   const size_t o_hist = take((size_t)(nhist + 1 + (nhist + 4095) / 4096) * 4);
   const size_t o_rec = take((size_t)n_v * rec_bytes(p.w));
+  // over-full unions (four-wave gridding kernel): counter, per-union first
+  // slot, slot list, partial grids
+  const bool split = grid_tile_compiled(3, p.w);
+  const int nslot = split ? union_slots(n_v) : 0;
+  const int64_t nunion = split ? (int64_t)(p.mx / 8) * (p.my / 8) : 0;
+  const size_t o_cnt = take(split ? 4 : 0);
+  const size_t o_uofs = take((size_t)nunion * 4);
+  const size_t o_slots = take((size_t)nslot * 8);
+  const size_t o_part = take((size_t)nslot * 64 * p.nf * sizeof(float2));
   const int64_t a_elems = std::max((int64_t)p.mx * p.my * p.nf, (int64_t)p.nx * p.ny * p.nz);
   const int64_t b_elems = std::max((int64_t)p.my * p.nx * p.nf, (int64_t)p.nx * p.ny * p.nz);
   const size_t o_a = take((size_t)a_elems * sizeof(float2));
@@ -507,10 +516,17 @@ size_t workspace_bytes(const Plan& p, int64_t n_pos, Workspace* ws, char* base) 
     ws->order = (int32_t*)(base + o_order);
     ws->order_alt = (int32_t*)(base + o_order2);
     ws->hist = (int32_t*)(base + o_hist);
+    ws->split_count = split ? (int32_t*)(base + o_cnt) : nullptr;
+    ws->uofs = (int32_t*)(base + o_uofs);
+    ws->slots = (int32_t*)(base + o_slots);
+    ws->partial = (float2*)(base + o_part);
     ws->rec = (void*)(base + o_rec);
     ws->region_a = (float2*)(base + o_a);
     ws->region_b = (float2*)(base + o_b);
   }
+  // the launch structure follows the slot count, also when a batch describes
+  // its launches without buffers
+  if (ws) ws->max_slots = nslot;
   return off;
 }
 

@@ -103,12 +103,31 @@ struct Workspace {
   int32_t* order = nullptr;       // [n_v] source index of each sorted sample
   int32_t* order_alt = nullptr;   // [n_v]
   int32_t* hist = nullptr;        // radix digit histograms (+ scan partial sums)
+  // over-full unions of the four-wave gridding kernel (null unless compiled for the width)
+  int32_t* split_count = nullptr; // [1] overflow slots taken (zeroed with the cell counts)
+  int32_t* uofs = nullptr;        // [unions] first overflow slot or -1
+  int32_t* slots = nullptr;       // [max_slots][2] union, part
+  float2* partial = nullptr;      // [max_slots][64][nf]
+  int max_slots = 0;
   void* rec = nullptr;            // [n_v] SampleRec<w>
   float2* region_a = nullptr;     // oversampled grid / spectrum / first inverse pass
   float2* region_b = nullptr;     // x-transformed grid / z profiles
 };
 
 size_t workspace_bytes(const Plan& p, int64_t n_pos, Workspace* ws, char* base);
+
+// over-full unions of the four-wave gridding kernel: samples per part and the
+// number of overflow slots a workspace holds for n_v virtual samples.  Every
+// sample lies in the streams of at most 4 unions, so 4 n_v / part length
+// bounds the slots ever needed; the table holds half that bound, at most 1024
+// slots (for 256 frequencies 128 MiB of partial grids), and a union whose
+// parts do not fit runs unsplit (the same sum, only slower).
+constexpr int kUnionPartLen = 2048;
+constexpr int kUnionMaxSlots = 1024;
+inline int union_slots(int64_t n_v) {
+  const int64_t b = (2 * n_v + kUnionPartLen - 1) / kUnionPartLen;
+  return (int)(b < kUnionMaxSlots ? b : kUnionMaxSlots);
+}
 
 // lateral NUFFT parameters for an oversampling (host only), their device
 // tables, and the tuning file (plan.cpp)

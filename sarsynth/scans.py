@@ -237,13 +237,15 @@ def config1_scan(seed: int = 0, snr_db: float = 20.0, with_echo: bool = True) ->
     return scan
 
 
-def clustered_scan(seed: int = 0, n_dwell: int = 4608, snr_db: float = 20.0) -> Scan:
+def clustered_scan(seed: int = 0, n_dwell: int = 4608, snr_db: float = 20.0, n_freq: int = 32) -> Scan:
     """The tiny scan's 512 shots plus n_dwell shots at one position (a hand
     that pauses in the middle of the aperture, the extreme of irregular
     freehand sampling): every pair of those shots lands on the same virtual
     element, so eight cells of the gridding grid hold n_dwell samples each.
-    Scene, sweep and image as the tiny scan."""
+    Scene and image as the tiny scan; n_freq frequencies over 77-81 GHz."""
     base = config1_scan(seed, snr_db, with_echo=False)
+    if n_freq != len(base.freq):
+        base.freq = sweep(n_freq)
     rng = _rng(6, seed)
     dwell = np.tile(base.pos[len(base.pos) // 2], (n_dwell, 1))
     pos = np.concatenate([base.pos, dwell], axis=0)

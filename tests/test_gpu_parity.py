@@ -287,6 +287,32 @@ def test_clustered_scan_matches_oracle(torch_cuda):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("nf", [32, 160])
+def test_clustered_scan_split_unions(torch_cuda, nf):
+    # the four-wave gridding kernel splits the unions over the dwell cells
+    # (over 4608 samples each, parts of 2048) into overflow workgroups and adds
+    # their partial grids in part order: equal to the unsplit one-wave tile up
+    # to summation order, reproducible, and at the oracle's image (the 4-tap
+    # kernel's single-point error, see the test above, bounds the distance)
+    from sarsynth import clustered_scan
+    scan = clustered_scan(0, n_freq=nf)
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, scan.grid)
+    plan = make_plan(scan)
+    assert plan.info["width"] == 4
+    pos, echo, _ = to_device(scan)
+    plan.set_grid_tile(3)
+    a = plan.reconstruct(pos, echo).cpu().numpy()
+    b = plan.reconstruct(pos, echo).cpu().numpy()
+    plan.set_grid_tile(0)
+    c = plan.reconstruct(pos, echo).cpu().numpy()
+    err, same = rel_l2(a, ref), rel_l2(a, c)
+    print(f"clustered scan, {nf} frequencies, split unions: vs unsplit tile {same:.2e}, vs oracle {err:.3e}")
+    assert np.array_equal(a, b)
+    assert same <= 1e-6
+    assert err <= 3e-3
+    assert peak_ok(a, ref)
+
+
 def test_empty_scan_gives_zero_image(torch_cuda, tiny):
     scan, _, _ = tiny
     plan = make_plan(scan)

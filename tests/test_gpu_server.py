@@ -230,7 +230,8 @@ def test_plan_destroy_is_busy_while_used(torch_cuda, mix):
     h = sar.sar_plan_create(sc.tx_xy, sc.rx_xy, sc.freq, sc.grid.nx, sc.grid.ny, sc.grid.nz, sc.grid.x0,
                             sc.grid.y0, sc.grid.z0, sc.grid.dx, sc.grid.dy, sc.grid.dz, sc.grid.z_ref,
                             sc.grid.z_focus, sc.n_pos)
-    srv = sar.Server(64 << 20)   # about one scan at a time: requests wait in the queue
+    need = sar.sar_plan_workspace_bytes(h, sc.n_pos)
+    srv = sar.Server(int(need * 1.5))   # one scan at a time: requests wait in the queue
     img = torch_cuda.empty((sc.grid.nx, sc.grid.ny, sc.grid.nz), dtype=torch_cuda.complex64, device="cuda")
     try:
         tickets = [sar.sar_submit(srv.handle, h, pos, sc.n_pos, echo, 1.0, img) for _ in range(4)]
