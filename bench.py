@@ -53,6 +53,34 @@ def recorded_traffic():
     return float(m_b.group(1))
 
 
+def cpu_model():
+    """The host CPU's model name (first processor entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def tiny_oracle_single_core():
+    """The FP64 oracle on the tiny scan with one BLAS thread, median of 3 (s)."""
+    import numpy as np
+    import oracle
+    from sarsynth import config1_scan
+    from threadpoolctl import threadpool_limits
+    scan = config1_scan(0)
+    ts = []
+    with threadpool_limits(limits=1):
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, scan.grid)
+            ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
 def cpu_baseline(scan, echo_host_fn):
     """The FP64 oracle (direct sums) timed on a bounded sample of the same scan:
     the 2-D non-uniform DFT for one of the N_f frequencies, the direct Stolt
@@ -88,10 +116,14 @@ def cpu_baseline(scan, echo_host_fn):
     del spec_part
     total = t_nudft * nf / k_sample + t_stolt * g.ny / rows + t_idft
     threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))))
+    t_single = tiny_oracle_single_core()
     return {
         "value": g.n_voxels / total,
         "unit": "voxels/s",
         "cores": threads,
+        "cpu_model": cpu_model(),
+        "host_cores_available": len(os.sched_getaffinity(0)),
+        "tiny_scan_oracle_single_core_ms": t_single * 1e3,
         "kind": "oracle",
         "sample": (f"direct 2-D NUDFT of all {scan.n_pos * scan.n_pair} virtual samples for {k_sample} of {nf} "
                    f"frequencies ({t_nudft:.1f} s), direct Stolt sum for {rows} of {g.ny} k_y rows "
@@ -629,6 +661,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "timer": ("HIP events recorded on the launch stream around the gridding stage of every timed step "
+                      "(split planning, spreading and combining kernels), mean over the steps"),
             "algorithmic_bytes_per_launch": alg_bytes,
             "measured_copy_GB_per_s": copy_gbps,
         },

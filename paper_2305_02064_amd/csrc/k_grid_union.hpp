@@ -442,8 +442,10 @@ struct UnionPlanBody {
   }
 };
 
-// Adds the partial grids of a split union to the grid, in part order: the
-// block of the union's first overflow slot does it for all 64 cells.
+// Adds the partial grids of a split union to the grid, in part order.  The
+// union's 64 cells x nf values are shared out over the blocks of its overflow
+// slots (one value range per slot), so the combine runs with as many blocks
+// as slots; each value still sums its parts 1, 2, ... in order.
 struct UnionCombineBody {
   struct Args {
     const int2* slots;
@@ -454,19 +456,30 @@ struct UnionCombineBody {
   };
   static constexpr int kThreads = 256;
   static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
-    const int s0 = (int)b;
-    if (s0 >= min(*a.counter, a.max_slots)) return;
-    const int2 e = a.slots[s0];
-    if (e.x < 0 || (e.y & 0xffff) != 1) return;
+    const int s = (int)b;
+    if (s >= min(*a.counter, a.max_slots)) return;
+    const int2 e = a.slots[s];
+    if (e.x < 0) return;
+    const int part = e.y & 0xffff;     // 1 .. parts
     const int parts = e.y >> 16;
+    const int s0 = s - (part - 1);     // the union's first slot
     const int x0 = (e.x % a.nux) * kUnionX, y0 = (e.x / a.nux) * kUnionY;
     const int per = kUnionX * kUnionY * a.nf;
-    for (int i = threadIdx.x; i < per; i += kThreads) {
+    const int lo = (int)((int64_t)per * (part - 1) / parts);
+    const int hi = (int)((int64_t)per * part / parts);
+    for (int i = lo + threadIdx.x; i < hi; i += kThreads) {
       const int cell = i / a.nf;
       const int f = i - cell * a.nf;
       float2* g = a.grid + ((int64_t)(y0 + cell / kUnionX) * a.mx + x0 + cell % kUnionX) * a.nf + f;
       float2 v = *g;
-      for (int q = 0; q < parts; ++q) v = cadd(v, a.partial[(int64_t)(s0 + q) * per + i]);
+      const float2* pp = a.partial + (int64_t)s0 * per + i;
+      int q = 0;
+      for (; q + 4 <= parts; q += 4) {   // four loads in flight, added in order
+        const float2 p0 = pp[(int64_t)q * per], p1 = pp[(int64_t)(q + 1) * per];
+        const float2 p2 = pp[(int64_t)(q + 2) * per], p3 = pp[(int64_t)(q + 3) * per];
+        v = cadd(cadd(cadd(cadd(v, p0), p1), p2), p3);
+      }
+      for (; q < parts; ++q) v = cadd(v, pp[(int64_t)q * per]);
       *g = v;
     }
   }
