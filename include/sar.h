@@ -87,6 +87,16 @@ typedef enum { SAR_ECHO_C64 = 0, SAR_ECHO_F16X2 = 1 } sar_echo_type;
  * weights each sample by the k_z interval it covers.  The paper states only
  * the k_z factor; off by default. */
 #define SAR_STOLT_DCF 0x4u
+/* Amplitude half of the compensation: besides exp(+j k beta) of Eq. (11),
+ * each sample is scaled by R^T R^R / R_0^2, the ratio between the multistatic
+ * amplitude of Eq. (9) and the planar monostatic one of Eq. (10), for a
+ * scatterer straight ahead of the sample's virtual element at the reference
+ * depth z_c (z_focus, or the z-centre of a depth slab):
+ *     ((d_x^2 + d_y^2) / 4 + (z_c - z_l)^2) / (z_c - Z_0)^2,
+ * with d the pair's Rx - Tx offset and z_l the shot's height.  The paper's
+ * compensation is phase only; off by default.  Independent of
+ * SAR_NO_COMPENSATION (which zeroes beta only). */
+#define SAR_AMPLITUDE 0x8u
 
 /* Plan descriptor: array geometry, frequency sweep and image grid.
  * Constraints (SAR_ERR_INVALID otherwise):

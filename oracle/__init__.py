@@ -31,6 +31,7 @@ from .geometry import (  # noqa: F401
     virtual_samples,
     residual_path,
     round_trip_quadratic,
+    amplitude_factor,
 )
 from .rma import (  # noqa: F401
     mode_axes,

@@ -82,3 +82,23 @@ def round_trip_quadratic(xv, yv, dx, dy, dz, z_ref, point):
     return (2.0 * r0 + 2.0 * (z0 - z) * dz / r0
             + (dx ** 2 + dy ** 2 + 4.0 * dz ** 2) / (4.0 * r0)
             - (((xv - x) * dx + (yv - y) * dy) ** 2 + 4.0 * (z0 - z) ** 2 * dz ** 2) / (4.0 * r0 ** 3))
+
+
+def amplitude_factor(pos, tx_xy, rx_xy, z_ref, z_focus):
+    """Amplitude half of the compensation: the ratio R^T R^R / R_0^2 that turns
+    the multistatic amplitude 1/(R^T R^R) of Eq. (9) into the planar monostatic
+    amplitude 1/R_0^2 of Eq. (10), evaluated for a reference scatterer straight
+    ahead of each virtual element, at (x', y', z_c) with z_c the scene (or
+    slab) reference depth.  R^T and R^R are the exact ranges of Eq. (2) from
+    the pair's Tx and Rx, R_0 the range of Eq. (6) from the virtual element on
+    the plane Z_0.  Returns [N_pos, n_tx * n_rx]; 1 for a monostatic element
+    on the plane."""
+    xT, yT, xR, yR, zl = tx_rx_coordinates(pos, tx_xy, rx_xy)
+    xv, yv = 0.5 * (xT + xR), 0.5 * (yT + yR)
+    zc = float(z_focus)
+    rt = np.sqrt((xT - xv) ** 2 + (yT - yv) ** 2 + (zl - zc) ** 2)
+    rr = np.sqrt((xR - xv) ** 2 + (yR - yv) ** 2 + (zl - zc) ** 2)
+    r0 = abs(zc - float(z_ref))
+    if r0 <= 0.0:
+        raise ValueError("scene reference depth must differ from the projection plane")
+    return rt * rr / r0 ** 2

@@ -34,7 +34,7 @@ import types
 
 import numpy as np
 
-from .geometry import residual_path, virtual_samples, wavenumber
+from .geometry import amplitude_factor, residual_path, virtual_samples, wavenumber
 
 
 def mode_axes(nx, ny, x0, y0, dx, dy):
@@ -46,12 +46,16 @@ def mode_axes(nx, ny, x0, y0, dx, dy):
     return kx, ky, x0 + (nx // 2) * dx, y0 + (ny // 2) * dy
 
 
-def compensate(echo, k, beta):
+def compensate(echo, k, beta, amp=None):
     """Multi-planar multistatic compensation, Eq. (11): s_hat = s exp(+j k beta).
 
-    echo [..., N_f], k [N_f], beta [...]; phase only (the amplitude mismatch
-    between Eqs. (9) and (10) is not corrected)."""
-    return np.asarray(echo, np.complex128) * np.exp(1j * np.asarray(beta)[..., None] * np.asarray(k)[None, :])
+    echo [..., N_f], k [N_f], beta [...].  The paper's compensation is phase
+    only; amp [...] (optional, amplitude_factor) also scales each sample by
+    the amplitude ratio between Eqs. (9) and (10)."""
+    out = np.asarray(echo, np.complex128) * np.exp(1j * np.asarray(beta)[..., None] * np.asarray(k)[None, :])
+    if amp is not None:
+        out = out * np.asarray(amp, np.float64)[..., None]
+    return out
 
 
 def nudft2(shat, xv, yv, kx, ky, xc, yc, block=8192):
@@ -139,13 +143,15 @@ def _virtual(pos, tx_xy, rx_xy, grid, compensation=True):
     return xv.ravel(), yv.ravel(), beta.ravel()
 
 
-def spectrum_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation=True):
+def spectrum_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation=True, amplitude=False):
     """Compensated spatial spectrum S [N_y, N_x, N_f] (Eqs. (3)-(4), (11)-(12),
-    step 1)."""
+    step 1); amplitude: also apply the amplitude half (amplitude_factor at the
+    grid's reference depth z_focus)."""
     k = wavenumber(freq)
     xv, yv, beta = _virtual(pos, tx_xy, rx_xy, grid, compensation)
     nf = len(k)
-    shat = compensate(np.asarray(echo).reshape(-1, nf), k, beta)
+    amp = amplitude_factor(pos, tx_xy, rx_xy, grid.z_ref, grid.z_focus).ravel() if amplitude else None
+    shat = compensate(np.asarray(echo).reshape(-1, nf), k, beta, amp)
     kx, ky, xc, yc = mode_axes(grid.nx, grid.ny, grid.x0, grid.y0, grid.dx, grid.dy)
     return nudft2(shat, xv, yv, kx, ky, xc, yc)
 
@@ -176,10 +182,10 @@ def image_planes_from_spectrum(spec, freq, grid, w_list, row_chunk=16, dcf=False
     return idft2(zc)
 
 
-def reconstruct_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation=True, dcf=False):
+def reconstruct_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation=True, dcf=False, amplitude=False):
     """Full image [N_x, N_y, N_z] of one scan (Fig. 3 pipeline, Eq. (16));
-    dcf: see rma_filter."""
-    spec = spectrum_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation)
+    dcf: see rma_filter; amplitude: see spectrum_direct."""
+    spec = spectrum_direct(pos, tx_xy, rx_xy, freq, echo, grid, compensation, amplitude)
     return image_from_spectrum(spec, freq, grid, dcf)
 
 
@@ -201,11 +207,13 @@ def slab_grids(grid, n_slabs):
     return out
 
 
-def reconstruct_slabs(pos, tx_xy, rx_xy, freq, echo, grid, n_slabs):
+def reconstruct_slabs(pos, tx_xy, rx_xy, freq, echo, grid, n_slabs, amplitude=False):
     """Image [N_x, N_y, N_z] with a reference depth per depth slab: slab j is
     the direct reconstruction of Eq. (16) on the slab's planes, compensated with
-    the slab's own reference depth (slab_grids)."""
+    the slab's own reference depth (slab_grids), in phase and, with amplitude,
+    in amplitude."""
     img = np.zeros((grid.nx, grid.ny, grid.nz), np.complex128)
     for j, g in enumerate(slab_grids(grid, n_slabs)):
-        img[:, :, j * g.nz:(j + 1) * g.nz] = reconstruct_direct(pos, tx_xy, rx_xy, freq, echo, g)
+        img[:, :, j * g.nz:(j + 1) * g.nz] = reconstruct_direct(pos, tx_xy, rx_xy, freq, echo, g,
+                                                                amplitude=amplitude)
     return img

@@ -19,7 +19,7 @@ namespace {
 
 struct GeoArgs {
   const double* pos;     // [n_pos][3]
-  const double* pair;    // [n_pair][4]: midpoint offset x, y; multistatic beta term; unused
+  const double* pair;    // [n_pair][4]: midpoint offset x, y; multistatic beta term; |d|^2 / 4
   int64_t n_v;
   int n_pair;
   double xc, yc;         // lateral centre of the image grid
@@ -28,6 +28,7 @@ struct GeoArgs {
   double z_ref;
   double beta_sign;      // 2 sign(Z_0 - z_c), or 0 without compensation
   double kb_beta, inv_i0_beta;
+  double z_c, amp_inv_r2;  // amplitude half: reference depth and 1 / (z_c - Z_0)^2 (0: off)
   int fp32;              // precision diagnostic: offsets and beta in float32
 };
 
@@ -390,9 +391,17 @@ struct RecordsBody {
       r.beta = a.g.beta_sign * (a.g.pos[3 * m + 2] - a.g.z_ref) + a.g.pair[4 * l + 2];
     const double fx = (double)cx - gx;
     const double fy = (double)cy - gy;
+    // amplitude half of the compensation (ratio of the amplitudes of Eqs. (9)
+    // and (10) for a scatterer at the reference depth straight ahead of the
+    // virtual element), folded into the x weights
+    float amp = 1.0f;
+    if (a.g.amp_inv_r2 != 0.0) {
+      const double h = a.g.z_c - a.g.pos[3 * m + 2];
+      amp = (float)((a.g.pair[4 * l + 3] + h * h) * a.g.amp_inv_r2);
+    }
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-      r.wx[j] = kb_weight<W>(fx + j, a.g.kb_beta, a.g.inv_i0_beta);
+      r.wx[j] = amp * kb_weight<W>(fx + j, a.g.kb_beta, a.g.inv_i0_beta);
       r.wy[j] = kb_weight<W>(fy + j, a.g.kb_beta, a.g.inv_i0_beta);
     }
     a.rec[s] = r;
@@ -434,6 +443,8 @@ sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, in
   g.z_ref = p.z_ref;
   g.beta_sign = p.beta_sign;
   g.kb_beta = p.kb_beta;
+  g.z_c = p.z_focus;
+  g.amp_inv_r2 = p.amp_inv_r2;
   g.fp32 = (p.flags & SAR_FP32_ARGS) ? 1 : 0;
   // 1 / I0(beta) evaluated with the same series on the host
   {

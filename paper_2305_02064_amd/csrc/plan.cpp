@@ -293,7 +293,7 @@ sar_status validate_desc(const sar_plan_desc* d) {
     return fail(SAR_ERR_UNSUPPORTED, "upsample must be 0 or in [1.25, 4]");
   if (!(d->kernel_width == 0 || (d->kernel_width >= 3 && d->kernel_width <= kMaxWidth)))
     return fail(SAR_ERR_INVALID, "kernel_width must be 0 or 3..8");
-  if (d->flags & ~(SAR_NO_COMPENSATION | SAR_FP32_ARGS | SAR_STOLT_DCF))
+  if (d->flags & ~(SAR_NO_COMPENSATION | SAR_FP32_ARGS | SAR_STOLT_DCF | SAR_AMPLITUDE))
     return fail(SAR_ERR_INVALID, "unknown flag bits");
   if ((d->flags & SAR_FP32_ARGS) && (d->echo_type != SAR_ECHO_C64 || (d->kernel_width != 0 && d->kernel_width != 4)))
     return fail(SAR_ERR_UNSUPPORTED, "SAR_FP32_ARGS is compiled for complex64 echo and a 4-tap lateral kernel");
@@ -357,6 +357,9 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
     p.beta_sign = 2.0 * (p.z_ref > p.z_focus ? 1.0 : -1.0);
     p.inv4rc = 1.0 / (4.0 * std::fabs(p.z_focus - p.z_ref));
   }
+  // amplitude half: (|d|^2 / 4 + (z_c - z_l)^2) / (z_c - Z_0)^2, the |d|^2 / 4
+  // per pair in the pair table
+  p.amp_inv_r2 = (p.flags & SAR_AMPLITUDE) ? 1.0 / ((p.z_focus - p.z_ref) * (p.z_focus - p.z_ref)) : 0.0;
 
   // ---- tables ----
   std::vector<double> fcc(p.nf), kk(p.nf);
@@ -375,7 +378,7 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
       pair[4 * l + 0] = ox;
       pair[4 * l + 1] = oy;
       pair[4 * l + 2] = (sx * sx + sy * sy) * p.inv4rc;
-      pair[4 * l + 3] = 0.0;
+      pair[4 * l + 3] = 0.25 * (sx * sx + sy * sy);
     }
   const int WZ = p.wz;
   const double esb = p.es_beta;

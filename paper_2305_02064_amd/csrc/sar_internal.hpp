@@ -64,6 +64,7 @@ struct Plan {
   int mz = 0, wz = 0;        // Stolt grid and ES width
   double es_beta = 0;
   double beta_sign = 0, inv4rc = 0;  // beta = beta_sign * dz + (dx^2 + dy^2) * inv4rc
+  double amp_inv_r2 = 0;             // SAR_AMPLITUDE: 1 / (z_c - Z_0)^2, else 0
   // device tables
   double* d_fcc = nullptr;     // f_i / c (cycles per metre) [nf]
   double* d_k = nullptr;       // k_i = 2 pi f_i / c [nf]

@@ -33,6 +33,7 @@ SAR_ECHO_F16X2 = 1
 SAR_NO_COMPENSATION = 0x1
 SAR_FP32_ARGS = 0x2
 SAR_STOLT_DCF = 0x4
+SAR_AMPLITUDE = 0x8
 SAR_BATCH_NO_GRAPH = 0x1
 
 STAGES = ("geometry+sort", "gridding", "fft_x", "fft_y", "stolt", "ifft_y", "ifft_x")

@@ -361,10 +361,14 @@ def config4_scan(seed: int, with_echo: bool = True, device=None) -> Scan:
 
 def point_scan(nx_pos: int, ny_pos: int, pitch: float, target, n_freq: int, grid: ImageGrid,
                tx_xy=None, rx_xy=None, z_dev=None, seed: int = 0, jitter: float = 0.0,
-               f_start: float = 77e9, f_stop: float = 81e9) -> Scan:
+               f_start: float = 77e9, f_stop: float = 81e9, z_track: str = "uniform") -> Scan:
     """Planar (optionally jittered / multi-planar) lattice of shots around the
     origin imaging one unit point scatterer; monostatic unless a layout is
-    given.  z_dev: None, or the half-width of a uniform z deviation (m)."""
+    given.  z_dev: None, or the largest z deviation max |d^z| (m), drawn per
+    z_track: "uniform" (independent per shot, uniform in +-z_dev) or "curve"
+    (a semi-smooth random curve over the shots in order: a low-passed random
+    walk plus 10% white roughness, zero mean, scaled so that max |d^z| = z_dev,
+    the freehand tracks of Sec. V-A)."""
     rng = _rng(9, seed)
     if tx_xy is None:
         tx_xy = np.zeros((1, 2))
@@ -376,7 +380,17 @@ def point_scan(nx_pos: int, ny_pos: int, pitch: float, target, n_freq: int, grid
     if jitter:
         x = x + rng.uniform(-jitter, jitter, x.size)
         y = y + rng.uniform(-jitter, jitter, y.size)
-    z = np.zeros_like(x) if not z_dev else rng.uniform(-z_dev, z_dev, x.size)
+    if not z_dev:
+        z = np.zeros_like(x)
+    elif z_track == "uniform":
+        z = rng.uniform(-z_dev, z_dev, x.size)
+    elif z_track == "curve":
+        z = _smooth_walk(rng, x.size, 24, 1.0)
+        z = z + 0.1 * rng.standard_normal(x.size)
+        z = z - z.mean()
+        z = z * (z_dev / np.max(np.abs(z)))
+    else:
+        raise ValueError(f"unknown z_track {z_track!r}")
     pos = np.stack([x, y, z], axis=1)
     freq = sweep(n_freq, f_start, f_stop)
     tgt = np.asarray(target, np.float64).reshape(1, 3)

@@ -264,6 +264,25 @@ def test_stolt_jacobian_flag(torch_cuda, tiny, nz):
     assert rel_l2(plain, ref) > 0.05   # the flag changes the image
 
 
+def test_amplitude_flag(torch_cuda, tiny):
+    # SAR_AMPLITUDE: each sample also scaled by R^T R^R / R_0^2 at z_focus
+    # (oracle.amplitude_factor), folded into the gridding weights
+    from paper_2305_02064_amd import sar
+    scan, _, _ = tiny
+    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, scan.grid,
+                                    amplitude=True)
+    plan = sar.Plan(scan.tx_xy, scan.rx_xy, scan.freq, scan.grid, scan.n_pos, flags=sar.SAR_AMPLITUDE)
+    pos, echo, _ = to_device(scan)
+    img = plan.reconstruct(pos, echo).cpu().numpy()
+    plan.close()
+    err = rel_l2(img, ref)
+    print(f"amplitude half image rel-L2 {err:.3e}")
+    assert err <= IMAGE_TOL
+    assert peak_ok(img, ref)
+    plain = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, scan.grid)
+    assert rel_l2(plain, ref) > 3e-3   # the flag changes the image
+
+
 def test_clustered_scan_matches_oracle(torch_cuda):
     # 4608 of 5120 shots at one position: eight cells of 4608 samples each
     # (more than one 4096-sample tile of the radix sort), the tiles over them

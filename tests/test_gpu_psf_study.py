@@ -1,16 +1,28 @@
 """Point-spread function against scanning irregularity (the study of the
 paper's Fig. 4, Sec. V-A): one point at 0.5 m, 256 shots along y over
-+-12.5 cm with the 2Tx x 4Rx array, shot heights uniform in +-dz_max for
-dz_max = 0 .. 20 cm; images with and without the multi-planar compensation.
++-12.5 cm with the 2Tx x 4Rx array, shot heights along a semi-smooth random
+curve scaled to max |d^z| = dz_max for dz_max = 0, 5, 10, 15 and 20 cm (three
+curve shapes, each scaled through every setting); images with and without the
+multi-planar compensation.
 
-Reported per setting: the peak voxel, its magnitude, and the -3 dB widths
-along y and z, against Eq. (17) (delta_y = lambda_c R / (2 D_y),
-delta_z = c / (2 B); the -3 dB width of the sinc response is 0.886 delta).
-Checked: at dz_max = 0 the widths match Eq. (17) within 15%; at every dz_max
-the compensated image keeps its peak on the point (within one voxel along y,
-within half the range resolution along z) and stronger than the uncompensated
-one; one compensated setting equals the oracle.  The shots form one line at
-x = 0, so the image has no resolution along x and x is not checked.
+The shots form one line at x = 0 and the array is collinear with it, so there
+is no aperture along x: every x column of the volume holds the point's
+response folded by the lateral transform's period, and the sum over x is the
+k_x = 0 column, i.e. the (y, z) image of the line scan, which is what the
+PSF cuts are taken from.  Reported per setting: the peak, its magnitude, the
+-3 dB widths along y and z and the peak sidelobe level along y, against
+Eq. (17) (delta_y = lambda_c R / (2 D_y), delta_z = c / (2 B); the -3 dB width
+of the sinc response is 0.886 delta).
+
+Checked: at dz_max = 0 the peak is on the point and the widths match Eq. (17)
+within 15%; averaged over the curve shapes, the peak magnitude falls, the
+lateral -3 dB width grows and the lateral sidelobes rise as dz_max grows
+(the paper's direct relationship between dz_max and the main beamwidth, with
+decreased sidelobe suppression); the width along z grows too but stays within
+25% of the linear case (the paper's "suffers ... but remains similar"); the
+compensated peak stays within 8 mm laterally and half a range-resolution cell
+in depth of the point and above the uncompensated one; one compensated setting
+equals the oracle.
 """
 
 import numpy as np
@@ -25,6 +37,8 @@ pytestmark = pytest.mark.gpu
 LAM = oracle.C0 / 79e9
 ZT = 0.5
 NY, NZ, DZ = 256, 128, 2.5e-3
+DZ_MAX = (0.0, 0.05, 0.10, 0.15, 0.20)
+SHAPES = (1, 2, 3)
 
 
 @pytest.fixture(scope="module")
@@ -51,58 +65,90 @@ def _fwhm(profile, pitch):
     return (xr - xl) * pitch
 
 
-def _setting(dz_max):
+def _sidelobe_db(profile):
+    """Largest level outside the main lobe (bounded by the first minima on
+    either side of the peak), in dB under the peak."""
+    a = np.abs(profile) / np.abs(profile).max()
+    i = int(np.argmax(a))
+    l, r = i, i
+    while l > 0 and a[l - 1] < a[l]:
+        l -= 1
+    while r < len(a) - 1 and a[r + 1] < a[r]:
+        r += 1
+    side = np.concatenate([a[:l], a[r + 1:]])
+    return float(20 * np.log10(side.max())) if side.size else -np.inf
+
+
+def _setting(dz_max, shape):
     pitch = 0.25 / (NY - 1)
     grid = ImageGrid(nx=8, ny=NY, nz=NZ, x0=-4 * LAM / 4, y0=-(NY // 2) * pitch, z0=ZT - (NZ // 2) * DZ,
                      dx=LAM / 4, dy=pitch, dz=DZ, z_ref=0.0, z_focus=ZT)
     tx, rx = awr1443_layout()
     scan = point_scan(1, NY, pitch, (0.0, 0.0, ZT), 64, grid, tx_xy=tx, rx_xy=rx,
-                      z_dev=dz_max if dz_max > 0 else None, seed=int(dz_max * 1000) + 7)
+                      z_dev=dz_max if dz_max > 0 else None, seed=shape, z_track="curve")
     return scan, pitch
 
 
 def _measure(img, pitch):
-    mag = np.abs(img)
-    u, v, w = np.unravel_index(int(np.argmax(mag)), img.shape)
-    return {"peak": (int(u), int(v), int(w)), "mag": float(mag[u, v, w]),
-            "wy_mm": 1e3 * _fwhm(img[u, :, w], pitch), "wz_mm": 1e3 * _fwhm(img[u, v, :], DZ)}
+    yz = img.sum(axis=0)
+    mag = np.abs(yz)
+    v, w = np.unravel_index(int(np.argmax(mag)), yz.shape)
+    return {"peak": (int(v), int(w)), "mag": float(mag[v, w]),
+            "wy_mm": 1e3 * _fwhm(yz[:, w], pitch), "wz_mm": 1e3 * _fwhm(yz[v, :], DZ),
+            "psl_y_db": _sidelobe_db(yz[:, w])}
 
 
 def test_psf_against_irregularity(torch_cuda):
     from paper_2305_02064_amd import sar
     truth_v, truth_w = NY // 2, NZ // 2
-    rows = []
-    for dz_max in (0.0, 0.05, 0.10, 0.20):
-        scan, pitch = _setting(dz_max)
-        pos = torch_cuda.from_numpy(scan.pos).cuda()
-        echo = torch_cuda.from_numpy(scan.echo.astype(np.complex64)).cuda()
-        res = {}
-        for name, flags in (("compensated", 0), ("uncompensated", sar.SAR_NO_COMPENSATION)):
-            plan = sar.Plan(scan.tx_xy, scan.rx_xy, scan.freq, scan.grid, scan.n_pos, flags=flags)
-            img = plan.reconstruct(pos, echo).cpu().numpy()
-            res[name] = _measure(img, pitch)
-            if name == "compensated" and dz_max == 0.10:
-                ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, scan.grid)
-                err = rel_l2(img, ref)
-                print(f"dz_max 10 cm compensated vs oracle: rel-L2 {err:.3e}")
-                assert err <= 1e-3
-            plan.close()
-        rows.append((dz_max, res))
+    table = {}
+    for shape in SHAPES:
+        for dz_max in DZ_MAX:
+            scan, pitch = _setting(dz_max, shape)
+            pos = torch_cuda.from_numpy(scan.pos).cuda()
+            echo = torch_cuda.from_numpy(scan.echo.astype(np.complex64)).cuda()
+            res = {}
+            for name, flags in (("compensated", 0), ("uncompensated", sar.SAR_NO_COMPENSATION)):
+                plan = sar.Plan(scan.tx_xy, scan.rx_xy, scan.freq, scan.grid, scan.n_pos, flags=flags)
+                img = plan.reconstruct(pos, echo).cpu().numpy()
+                res[name] = _measure(img, pitch)
+                if name == "compensated" and dz_max == 0.10 and shape == SHAPES[0]:
+                    ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo,
+                                                    scan.grid)
+                    err = rel_l2(img, ref)
+                    print(f"dz_max 10 cm compensated vs oracle: rel-L2 {err:.3e}")
+                    assert err <= 1e-3
+                plan.close()
+            table[(shape, dz_max)] = res
     d_y = NY * (0.25 / (NY - 1))
     wy_th = 1e3 * 0.886 * LAM * ZT / (2 * d_y)
     wz_th = 1e3 * 0.886 * oracle.C0 / (2 * 4e9)
     print(f"Eq. (17) -3 dB widths: y {wy_th:.2f} mm, z {wz_th:.1f} mm")
-    print("dz_max | compensated: peak, |o|, w_y, w_z | uncompensated: peak, |o|, w_y, w_z")
-    for dz_max, res in rows:
+    print("shape dz_max | compensated: peak (v, w), |o|, w_y, w_z, sidelobe_y | uncompensated: peak, |o|")
+    for (shape, dz_max), res in table.items():
         c, u = res["compensated"], res["uncompensated"]
-        print(f"{dz_max * 100:4.0f} cm | {c['peak']} {c['mag']:.3g} {c['wy_mm']:.2f} {c['wz_mm']:.1f} | "
-              f"{u['peak']} {u['mag']:.3g} {u['wy_mm']:.2f} {u['wz_mm']:.1f}")
-    c0 = rows[0][1]["compensated"]
+        print(f"{shape} {dz_max * 100:4.0f} cm | {c['peak']} {c['mag']:.3g} {c['wy_mm']:.2f} {c['wz_mm']:.1f} "
+              f"{c['psl_y_db']:.1f} dB | {u['peak']} {u['mag']:.3g}")
+    mean = {dz: {k: float(np.mean([table[(s, dz)]["compensated"][k] for s in SHAPES]))
+                 for k in ("mag", "wy_mm", "wz_mm", "psl_y_db")} for dz in DZ_MAX}
+    print("mean over shapes: dz_max | |o|, w_y, w_z, sidelobe_y")
+    for dz in DZ_MAX:
+        m = mean[dz]
+        print(f"{dz * 100:4.0f} cm | {m['mag']:.3g} {m['wy_mm']:.2f} {m['wz_mm']:.1f} {m['psl_y_db']:.1f} dB")
+
+    c0 = table[(SHAPES[0], 0.0)]["compensated"]
+    assert c0["peak"] == (truth_v, truth_w)
     assert abs(c0["wy_mm"] / wy_th - 1) < 0.15
     assert abs(c0["wz_mm"] / wz_th - 1) < 0.15
-    for dz_max, res in rows:
+    for a, b in zip(DZ_MAX, DZ_MAX[1:]):
+        assert mean[b]["mag"] < mean[a]["mag"], (a, b)
+        assert mean[b]["wy_mm"] > mean[a]["wy_mm"], (a, b)
+        assert mean[b]["psl_y_db"] > mean[a]["psl_y_db"], (a, b)
+        assert mean[b]["wz_mm"] > mean[a]["wz_mm"], (a, b)
+    for (shape, dz_max), res in table.items():
         c, u = res["compensated"], res["uncompensated"]
-        assert abs(c["peak"][1] - truth_v) <= 1, (dz_max, c["peak"])
-        assert abs(c["peak"][2] - truth_w) * DZ <= 0.5 * oracle.C0 / (2 * 4e9), (dz_max, c["peak"])
+        assert c["wz_mm"] <= 1.25 * c0["wz_mm"], (shape, dz_max)
+        assert abs(c["peak"][0] - truth_v) * pitch <= 8e-3, (shape, dz_max, c["peak"])
+        assert abs(c["peak"][1] - truth_w) * DZ <= 0.5 * oracle.C0 / (2 * 4e9), (shape, dz_max, c["peak"])
         if dz_max > 0:
-            assert c["mag"] > u["mag"], dz_max
+            assert c["mag"] > u["mag"], (shape, dz_max)

@@ -182,6 +182,50 @@ def test_compensation_recovers_planar_model():
     assert np.abs(shat - ref).max() < 1e-12 * np.abs(ref).max()
 
 
+def test_amplitude_factor_restores_the_planar_amplitude():
+    # the amplitude half of the compensation: for a scatterer straight ahead of
+    # a virtual element at the reference depth z_c, the echo of Eq. (9) (built
+    # by the input generator with exact ranges and amplitude 1/(R^T R^R))
+    # scaled by the factor has the planar amplitude 1/R_0^2 of Eq. (10), for
+    # tilted shots (d^z != 0) and every Tx/Rx pair; without it the amplitude is
+    # off by up to tens of percent
+    rng = np.random.default_rng(11)
+    tx = np.array([[-0.03, 0.0], [0.03, 0.01]])
+    rx = np.array([[-0.01, 0.0], [0.01, -0.02], [0.0, 0.02]])
+    z_ref, z_c = 0.0, 0.25
+    pos = np.stack([rng.uniform(-0.05, 0.05, 6), rng.uniform(-0.05, 0.05, 6), rng.uniform(-0.03, 0.03, 6)], 1)
+    freq = sweep(4)
+    k = oracle.wavenumber(freq)
+    xv, yv, dx, dy, dz = oracle.virtual_samples(pos, tx, rx, z_ref)
+    amp = oracle.amplitude_factor(pos, tx, rx, z_ref, z_c)
+    beta = oracle.residual_path(dx, dy, dz, z_ref, z_c)
+    worst_without = 0.0
+    for m in range(len(pos)):
+        for l in range(len(tx) * len(rx)):
+            tgt = np.array([[xv[m, l], yv[m, l], z_c]])
+            s = synth_echo_numpy(pos[m:m + 1], tx, rx, freq, tgt, np.ones(1, np.complex128))[0, l]
+            shat = oracle.compensate(s[None, :], k, beta[m, l:l + 1], amp[m, l:l + 1])[0]
+            planar = 1.0 / (z_c - z_ref) ** 2
+            assert np.abs(np.abs(shat) / planar - 1).max() < 1e-12
+            worst_without = max(worst_without, float(np.abs(np.abs(s) / planar - 1).max()))
+    assert worst_without > 0.1
+    # a monostatic element on the projection plane needs no amplitude change
+    on_plane = np.stack([pos[:, 0], pos[:, 1], np.full(len(pos), z_ref)], 1)
+    z2 = np.zeros((1, 2))
+    assert np.array_equal(oracle.amplitude_factor(on_plane, z2, z2, z_ref, z_c), np.ones((len(pos), 1)))
+
+
+def test_one_slab_with_amplitude_is_the_single_depth_image_with_amplitude():
+    sc = depth_pair_scan(n_side=8, n_freq=4)
+    g = sc.grid
+    o1 = oracle.reconstruct_slabs(sc.pos, sc.tx_xy, sc.rx_xy, sc.freq, sc.echo, g, 1, amplitude=True)
+    gc = dataclasses.replace(g, z_focus=g.z0 + 0.5 * (g.nz - 1) * g.dz)
+    o2 = oracle.reconstruct_direct(sc.pos, sc.tx_xy, sc.rx_xy, sc.freq, sc.echo, gc, amplitude=True)
+    assert np.array_equal(o1, o2)
+    o3 = oracle.reconstruct_direct(sc.pos, sc.tx_xy, sc.rx_xy, sc.freq, sc.echo, gc)
+    assert _rel(o2, o3) > 1e-3
+
+
 # --------------------------------------------------------------------------
 # 2-D non-uniform DFT
 # --------------------------------------------------------------------------
