@@ -46,6 +46,12 @@ __device__ __forceinline__ void store_stream(float2* p, float2 v) {
   const f2_vec w = {v.x, v.y};
   __builtin_nontemporal_store(w, (f2_vec*)p);
 }
+// two adjacent complex values in one 16-byte streaming store (p 16-byte aligned)
+typedef float f4_vec __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_stream2(float2* p, float2 v0, float2 v1) {
+  const f4_vec w = {v0.x, v0.y, v1.x, v1.y};
+  __builtin_nontemporal_store(w, (f4_vec*)p);
+}
 
 // the same with the argument formed and reduced in float32 (precision diagnostic)
 __device__ __forceinline__ float2 cis_cycles_f32(float t) {

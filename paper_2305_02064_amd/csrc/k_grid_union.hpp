@@ -2,8 +2,9 @@
 // (Eq. (11)) and Kaiser-Bessel gridding with each compensated echo value
 // shared by the four waves of a workgroup.
 //
-// A workgroup owns a union of 8 x 8 grid cells for 128 frequencies (two per
-// lane).  Wave w owns the union's rows w and w + 4, all 8 columns: 2 x 8 x 2
+// A workgroup owns a union of 8 x 8 grid cells for 128 frequencies (two
+// adjacent ones per lane, so a lane reads a sample's values with one 16-byte
+// LDS load and writes each cell with one 16-byte store).  Wave w owns the union's rows w and w + 4, all 8 columns: 2 x 8 x 2
 // complex accumulators per lane.  Every sample whose W x W support (W <= 4)
 // touches the union covers W consecutive rows, so it lands in at most one row
 // of each wave and every wave visits nearly every sample once: the waves stay
@@ -111,7 +112,7 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
   double fcc[FPL];
 #pragma unroll
   for (int h = 0; h < FPL; ++h) {
-    fq[h] = fbase + 64 * h + lane;
+    fq[h] = fbase + FPL * lane + h;
     fcc[h] = a.fcc[fq[h] < a.nf ? fq[h] : a.nf - 1];
   }
   // runs of first-tap cells: row j (y offset j - (W-1)), x in [ux0 - (W-1), ux0 + UX)
@@ -261,24 +262,30 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
     // s_hat = s exp(+j 2 pi f beta / c), float64 argument reduced mod a cycle
     for (int k = wv; k < n; k += NWV) {
       const double bk = readlane_f64(beta0, k);
+      // the row sits in LDS in frequency order (complex64, or half pairs in
+      // the first half of the slot); the lane's two values are adjacent
       float2 t2[FPL];
+      if constexpr (ET != SAR_ECHO_F16X2) {
+        const float4 t4 = *(const float4*)(buf + VOFF + k * EB + lane * 16);
+        t2[0] = make_float2(t4.x, t4.y);
+        t2[1] = make_float2(t4.z, t4.w);
+      } else {
+        const __half2* hp = (const __half2*)(buf + VOFF + k * EB + lane * 8);
 #pragma unroll
-      for (int h = 0; h < FPL; ++h) {
-        if constexpr (ET != SAR_ECHO_F16X2) {
-          t2[h] = *(const float2*)(buf + VOFF + k * EB + h * 512 + lane * 8);
-        } else {
-          const float2 w2 = __half22float2(*(const __half2*)(buf + VOFF + k * EB + h * 256 + lane * 4));
+        for (int h = 0; h < FPL; ++h) {
+          const float2 w2 = __half22float2(hp[h]);
           t2[h] = make_float2(w2.x * a.echo_scale, w2.y * a.echo_scale);
         }
       }
+      float2 u2[FPL];
 #pragma unroll
       for (int h = 0; h < FPL; ++h) {
         if constexpr (ET == kEchoC64Fp32Args)
-          *(float2*)(buf + VOFF + k * EB + h * 512 + lane * 8) =
-              cmul(t2[h], cis_cycles_f32((float)bk * (float)fcc[h]));
+          u2[h] = cmul(t2[h], cis_cycles_f32((float)bk * (float)fcc[h]));
         else
-          *(float2*)(buf + VOFF + k * EB + h * 512 + lane * 8) = cmul(t2[h], cis_cycles(bk * fcc[h]));
+          u2[h] = cmul(t2[h], cis_cycles(bk * fcc[h]));
       }
+      *(float4*)(buf + VOFF + k * EB + lane * 16) = make_float4(u2[0].x, u2[0].y, u2[1].x, u2[1].y);
     }
     // weight products: thread t forms product (jj, kk) of sample t / 16
     {
@@ -302,7 +309,7 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
     const uint32_t cxy1 = gather_cxy(sidx1);
     int k = 0;
     typedef __attribute__((address_space(3))) char lds_char;
-    const uint32_t vbase = (uint32_t)(uintptr_t)(lds_char*)buf + (uint32_t)(VOFF + 8 * lane);
+    const uint32_t vbase = (uint32_t)(uintptr_t)(lds_char*)buf + (uint32_t)(VOFF + 16 * lane);
     const uint32_t pbase = (uint32_t)(uintptr_t)(lds_char*)(buf + POFF);
     // one sample with its tap pattern fixed at compile time: I = (row offset
     // of its last tap from this wave's first row + NWV - 1) * NBX + column
@@ -318,18 +325,18 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
       if constexpr (R0 < RPW && JJ >= 0 && JJ < W) {
         typedef float f2v __attribute__((ext_vector_type(2)));
         typedef float f4v __attribute__((ext_vector_type(4)));
-        f2v r0, r1;
+        f4v r;
         f4v q;
         const uint32_t va = vbase + (uint32_t)(k * EB);
         const uint32_t pa = pbase + (uint32_t)(k * 64);
         asm volatile(
-            "ds_read_b64 %0, %3\n\tds_read_b64 %1, %3 offset:512\n\t"
-            "ds_read_b128 %2, %4 offset:%5\n\ts_waitcnt lgkmcnt(0)"
-            : "=&v"(r0), "=&v"(r1), "=&v"(q)
+            "ds_read_b128 %0, %2\n\t"
+            "ds_read_b128 %1, %3 offset:%4\n\ts_waitcnt lgkmcnt(0)"
+            : "=&v"(r), "=&v"(q)
             : "v"(va), "v"(pa), "i"(JJ * 16)
             : "memory");
         const float wp[4] = {q.x, q.y, q.z, q.w};
-        const float2 v[FPL] = {make_float2(r0.x, r0.y), make_float2(r1.x, r1.y)};
+        const float2 v[FPL] = {make_float2(r.x, r.y), make_float2(r.z, r.w)};
         static_for<0, W>([&](auto kc) __attribute__((always_inline)) {
           constexpr int kk = decltype(kc)::value;
           constexpr int cc = BB - (W - 1) + kk;
@@ -385,14 +392,27 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
     gbase = a.partial + ((int64_t)slot * UX * UY + wv * UX) * a.nf;
     rstride = (int64_t)UX * a.nf;
   }
-#pragma unroll
-  for (int h = 0; h < FPL; ++h) {
-    if (fbase + 64 * h + off < a.nf) {
-      float2* g = gbase + fbase + 64 * h + off;
+  // the lane's two adjacent frequencies: one 16-byte store per cell when both
+  // exist and the cells start on 16 bytes (even nf)
+  const int f0 = fbase + FPL * off;
+  if (f0 < a.nf) {
+    float2* g = gbase + f0;
+    if (quad_ok) {
 #pragma unroll
       for (int r = 0; r < RPW; ++r)
 #pragma unroll
-        for (int c = 0; c < UX; ++c) store_stream(g + NWV * r * rstride + (int64_t)c * a.nf, acc[r][c][h]);
+        for (int c = 0; c < UX; ++c)
+          store_stream2(g + NWV * r * rstride + (int64_t)c * a.nf, acc[r][c][0], acc[r][c][1]);
+    } else {
+      const bool second = f0 + 1 < a.nf;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+#pragma unroll
+        for (int c = 0; c < UX; ++c) {
+          float2* q = g + NWV * r * rstride + (int64_t)c * a.nf;
+          store_stream(q, acc[r][c][0]);
+          if (second) store_stream(q + 1, acc[r][c][1]);
+        }
     }
   }
 }

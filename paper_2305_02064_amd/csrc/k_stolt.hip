@@ -24,6 +24,7 @@
 // transform instead).
 
 #include "device_common.hpp"
+#include "es_poly.hpp"
 #include "launch.hpp"
 #include "sar_internal.hpp"
 
@@ -44,19 +45,27 @@ struct StoltArgs {
   double dkx, dky;
   double zmid_minus_zref_cyc;  // (z_mid - Z_0) / (2 pi)
   double dz_cells;             // dz * MZ / (2 pi)
-  float es_beta;
   int dcf;             // 1: filter factor 4k (k_z times the Jacobian dk_z/dk = 4k/k_z)
   int sgx, sgy;        // 1: fold (-1)^P (resp. (-1)^Q) in (even nx, ny)
   int64_t ncol;
 };
 
-// exponential-of-semicircle kernel exp(beta (sqrt(1 - z^2) - 1)) at z = 2 d / WZ
-// (d the signed distance in cells), written exp2(b2 sqrt(1 - z^2) - b2) with
-// b2 = beta log2(e); the hardware square root and exp2 (about 1 ulp each) are
-// ample for a kernel weight
-__device__ __forceinline__ float es_weight(float z, float b2) {
-  const float q = fmaf(-z, z, 1.f);
-  return q > 0.f ? __builtin_amdgcn_exp2f(fmaf(b2, __builtin_amdgcn_sqrtf(q), -b2)) : 0.f;
+// The WZ weights of the exponential-of-semicircle kernel
+// exp(beta (sqrt(1 - z^2) - 1)) at z = 2 d_s / WZ, d_s = tau + s - WZ/2 the
+// distance of tap s from the sample, as polynomials in t = 2 tau - 1 (fitted
+// per tap, es_poly.hpp; error about exp(-beta), the kernel's own value at the
+// edge of its support): WZ x degree FMAs per sample instead of a square root
+// and an exponential per tap
+template <int WZ>
+__device__ __forceinline__ void es_taps(float t, float (&w)[WZ]) {
+  using P = EsPoly<WZ>;
+#pragma unroll
+  for (int s = 0; s < WZ; ++s) {
+    float v = P::c[s][0];
+#pragma unroll
+    for (int j = 1; j <= P::kDeg; ++j) v = fmaf(v, t, P::c[s][j]);
+    w[s] = v;
+  }
 }
 
 // square root of a positive, normal float64: hardware reciprocal square root
@@ -99,7 +108,6 @@ __device__ __forceinline__ void StoltBody<MZ, WZ, F32>::run(const StoltArgs& a, 
   float2* g = grid[cl];
   const int per = (a.nf + kG - 1) / kG;  // contiguous frequencies per lane
   const int64_t ngroups = (a.ncol + kCols - 1) / kCols;
-  const float b2 = a.es_beta * 1.4426950408889634f;  // beta log2(e)
 
   // one batch of the lane's run: wavenumbers and spectrum values, all loads
   // issued before any is used (a bit of `valid` per sample marks the ones
@@ -188,17 +196,24 @@ __device__ __forceinline__ void StoltBody<MZ, WZ, F32>::run(const StoltArgs& a, 
             gc = kz * a.dz_cells;
           }
           const float2 v = cscale(cmul(sb[r], ph), kzs * sgn);
-          const int c0 = (int)floor(gc - 0.5 * WZ) + 1;
+          const double a0 = gc - 0.5 * WZ;
+          const double c0d = floor(a0) + 1.0;
+          const int c0 = (int)c0d;
           if (!open || c0 < wb || c0 + WZ > wb + WWIN) {
             if (open) flush();
             wb = c0;
             open = true;
           }
-          const float z0 = (float)((double)wb - gc) * (2.f / (float)WZ);
+          float wt[WZ];
+          es_taps<WZ>((float)(2.0 * (c0d - a0) - 1.0), wt);
+          // tap s lands in window cell o + s, o = c0 - wb in 0 .. WWIN - WZ
+          const int o = c0 - wb;
 #pragma unroll
           for (int s2 = 0; s2 < WWIN; ++s2) {
-            const float wgt = es_weight(fmaf((float)s2, 2.f / (float)WZ, z0), b2);
-            cfma(win[s2], v, wgt);
+            const float w0 = s2 < WZ ? wt[s2] : 0.f;
+            const float w1 = s2 >= 1 && s2 - 1 < WZ ? wt[s2 - 1] : 0.f;
+            const float w2 = s2 >= 2 && s2 - 2 < WZ ? wt[s2 - 2] : 0.f;
+            cfma(win[s2], v, o == 0 ? w0 : (o == 1 ? w1 : w2));
           }
         }
       }
@@ -326,6 +341,9 @@ sar_status stolt_mz(const Plan& p, const StoltArgs& a, LaunchSink& sink) {
   const int64_t ngroups = (a.ncol + kCols - 1) / kCols;
   const int64_t nblk = ngroups < 256 * 72 ? ngroups : 256 * 72;
   const bool f32 = (p.flags & SAR_FP32_ARGS) != 0;
+  // the compiled tap polynomials are fitted for beta = 2.30 WZ
+  if (!((p.wz == 6 && p.es_beta == EsPoly<6>::kBeta) || (p.wz == 8 && p.es_beta == EsPoly<8>::kBeta)))
+    return fail(SAR_ERR_UNSUPPORTED, "Stolt kernel shape not compiled");
   switch (p.wz) {
     case 6:
       return f32 ? launch_body<StoltBody<MZ, 6, true>>(sink, (uint32_t)nblk, 0, a, "stolt launch")
@@ -374,7 +392,6 @@ sar_status launch_stolt(const Plan& p, const float2* spec, float2* zcube, Launch
   const double zmid = p.z0 + (p.nz / 2) * p.dz;
   a.zmid_minus_zref_cyc = (zmid - p.z_ref) / (2.0 * M_PI);
   a.dz_cells = p.dz * p.mz / (2.0 * M_PI);
-  a.es_beta = (float)p.es_beta;
   a.dcf = (p.flags & SAR_STOLT_DCF) ? 1 : 0;
   a.sgx = (p.nx & 1) ? 0 : 1;
   a.sgy = (p.ny & 1) ? 0 : 1;
