@@ -81,6 +81,22 @@ def tiny_oracle_single_core():
     return float(np.median(ts))
 
 
+def tiny_bpa_oracle(planes=1):
+    """The FP64 oracle's direct back-projection (exact ranges) of the tiny
+    scan on the host, timed on `planes` of its z planes and extrapolated to
+    the whole image (s)."""
+    import dataclasses
+    import oracle
+    from sarsynth import config1_scan
+    scan = config1_scan(0)
+    g = scan.grid
+    sub = dataclasses.replace(g, nz=planes)
+    t0 = time.perf_counter()
+    oracle.bpa(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, sub)
+    t = time.perf_counter() - t0
+    return t * g.nz / planes, f"{planes} of {g.nz} z planes ({t:.1f} s), extrapolated"
+
+
 def cpu_baseline(scan, echo_host_fn):
     """The FP64 oracle (direct sums) timed on a bounded sample of the same scan:
     the 2-D non-uniform DFT for one of the N_f frequencies, the direct Stolt
@@ -117,6 +133,7 @@ def cpu_baseline(scan, echo_host_fn):
     total = t_nudft * nf / k_sample + t_stolt * g.ny / rows + t_idft
     threads = int(os.environ.get("OPENBLAS_NUM_THREADS", os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0)))))
     t_single = tiny_oracle_single_core()
+    t_bpa, bpa_how = tiny_bpa_oracle()
     return {
         "value": g.n_voxels / total,
         "unit": "voxels/s",
@@ -124,6 +141,8 @@ def cpu_baseline(scan, echo_host_fn):
         "cpu_model": cpu_model(),
         "host_cores_available": len(os.sched_getaffinity(0)),
         "tiny_scan_oracle_single_core_ms": t_single * 1e3,
+        "tiny_scan_bpa_oracle_s": t_bpa,
+        "tiny_scan_bpa_oracle_sample": bpa_how,
         "kind": "oracle",
         "sample": (f"direct 2-D NUDFT of all {scan.n_pos * scan.n_pair} virtual samples for {k_sample} of {nf} "
                    f"frequencies ({t_nudft:.1f} s), direct Stolt sum for {rows} of {g.ny} k_y rows "
@@ -535,6 +554,25 @@ def clustered_bench(plan, pos, echo, image, stream, reps=10):
             "stage_ms": {k: v / max(n_calls, 1) for k, v in stage_ms.items()}}
 
 
+def slab_bench(scan, pos, echo, n_slabs=4, reps=5):
+    """The large scan with a reference depth per depth slab (n_slabs sub-plans:
+    one front end per slab, each slab's back end on its planes); milliseconds
+    per scan, mean of reps calls."""
+    import torch
+    from paper_2305_02064_amd import sar
+    plan = sar.Plan(scan.tx_xy, scan.rx_xy, scan.freq, scan.grid, scan.n_pos, n_slabs=n_slabs)
+    image = plan.new_image()
+    plan.reconstruct(pos, echo, image)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.reconstruct(pos, echo, image)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    plan.close()
+    return {"workload": f"large scan, {n_slabs} depth slabs", "n_slabs": n_slabs, "ms_per_scan": ms}
+
+
 def copy_calibration(nbytes, launches=3):
     import torch
     x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -562,6 +600,7 @@ def main():
                     help="Poisson rates for a sweep with every request's inputs in pinned host memory (opt-in)")
     ap.add_argument("--oracle-uneven", action="store_true",
                     help="also time the FP64 oracle beside the GPU on 12 scans of the uneven batch (minutes of CPU)")
+    ap.add_argument("--no-slabs", action="store_true", help="skip the depth-slab timing of the large scan")
     ap.add_argument("--clustered", action="store_true",
                     help="also time the large scan with a quarter of its shots at one position (a dwelling hand)")
     args = ap.parse_args()
@@ -681,6 +720,8 @@ def main():
         out["oracle_uneven"] = oracle_uneven()
     if args.clustered:
         out["clustered"] = clustered_bench(plan, pos, echo, image, stream)
+    if not args.no_slabs:
+        out["slabs"] = slab_bench(scan, pos, echo)
     print(json.dumps(out))
     plan.close()
 

@@ -5,8 +5,9 @@
 // items' launches by pipeline step, and groups launches of the same kernel
 // body at the same step into one fused grid (k_batch<Body>): item i owns a
 // contiguous, 8-aligned range of blocks and reads its arguments from a device
-// table.  Steps follow each other in stream order, so a scan's kernels keep
-// their order while different scans, of different sizes, share every launch.
+// table (items with more blocks take the lower block ranges).  Steps follow
+// each other in stream order, so a scan's kernels keep their order while
+// different scans, of different sizes, share every launch.
 //
 // Per-sample grids are sized for each plan's max_pos and stop at the call's
 // n_pos, and every pointer lives in the argument tables, so the launch
@@ -96,9 +97,29 @@ size_t build_groups(const std::vector<RecordSink>& sinks, std::vector<Group>& gr
       }
       g->items.push_back((int)it);
       g->rec_index.push_back((int)step);
-      g->blocks.push_back({g->total_blocks, r.nblocks});
-      g->total_blocks += (uint32_t)round_up(r.nblocks, 8);
+      g->blocks.push_back({0, r.nblocks});
     }
+  }
+  // block ranges: items with more blocks first (the hardware hands out blocks
+  // in index order, so the largest items start earliest and small ones fill
+  // the tail of the grid); ties keep item order
+  for (auto& g : groups) {
+    std::vector<size_t> order(g.items.size());
+    for (size_t e = 0; e < order.size(); ++e) order[e] = e;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return g.blocks[x].count > g.blocks[y].count; });
+    std::vector<int> items(order.size()), recs(order.size());
+    std::vector<BatchItem> blocks(order.size());
+    g.total_blocks = 0;
+    for (size_t e = 0; e < order.size(); ++e) {
+      items[e] = g.items[order[e]];
+      recs[e] = g.rec_index[order[e]];
+      blocks[e] = {g.total_blocks, g.blocks[order[e]].count};
+      g.total_blocks += (uint32_t)round_up(blocks[e].count, 8);
+    }
+    g.items.swap(items);
+    g.rec_index.swap(recs);
+    g.blocks.swap(blocks);
   }
   // each group's table is an array of the body's Args, indexed by the kernel
   // with stride sizeof(Args): entries are packed at exactly that stride
