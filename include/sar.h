@@ -253,15 +253,17 @@ sar_status sar_backproject(sar_plan plan, const double* d_pos, int64_t n_pos, co
  * oversampling (1.25, 1.5 and 2 when the plan was created with upsample = 0,
  * else only the requested one; the kernel width follows the plan's tolerance
  * at each) times every gridding tile configuration compiled for that width:
- *   0: 4 x 4 cells, 2 frequencies per lane (kernels of 3 to 8 taps);
- *   1: 8 x 8 cells, 1 frequency per lane (3 to 5 taps);
- *   2: 8 x 4 cells, 2 frequencies per lane (5 and 6 taps).
+ *   0: 4 x 4 cells per wave, 2 frequencies per lane (kernels of 3 to 8 taps);
+ *   1: 8 x 8 cells per wave, 1 frequency per lane (3 to 5 taps);
+ *   2: 8 x 4 cells per wave, 2 frequencies per lane (5 and 6 taps);
+ *   3: 8 x 8 cells per 4-wave workgroup, 2 frequencies per lane (3 and 4 taps).
  * Candidates whose workspace would exceed the plan's current
  * sar_plan_workspace_bytes(plan, n_pos) are skipped, so d_workspace as sized
  * before the call stays large enough.  Runs each candidate a few times on
  * `stream` and waits for them (synchronous).  The default before tuning:
- * oversampling 2, tile 1 when the sweep has at most 64 frequencies (and the
- * width allows it), else tile 0.  If the environment variable
+ * oversampling 2 (or the nearest 5-smooth grid, see upsample), tile 1 when the
+ * sweep has at most 64 frequencies (and the width allows it), else tile 3 for
+ * kernels of up to 4 taps, else tile 0.  If the environment variable
  * SAR_AUTOTUNE_FILE names a file, the choice is also stored there for the
  * plan's size bucket (image and sweep sizes, pairs, echo type, flags,
  * tolerance, n_pos rounded up to a power of two), and plans created later
@@ -273,7 +275,7 @@ sar_status sar_backproject(sar_plan plan, const double* d_pos, int64_t n_pos, co
 sar_status sar_plan_autotune(sar_plan plan, const double* d_pos, int64_t n_pos, const void* d_echo,
                              float echo_scale, void* d_workspace, sar_stream_t stream, int32_t* tile_out);
 
-/* Select a gridding tile configuration directly (0, 1 or 2, as listed for
+/* Select a gridding tile configuration directly (0 to 3, as listed for
  * sar_plan_autotune).  SAR_ERR_UNSUPPORTED if it is not compiled for the
  * plan's kernel width; same restrictions as sar_plan_autotune. */
 sar_status sar_plan_set_grid_tile(sar_plan plan, int32_t tile);
