@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "voxels/s + scans/s & p99 latency (served vs plain GPU) at ≤1e-3 rel-L2 vs FP64"
 HBM_PEAK_GBS = 8000.0
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_gridding_freehand-512x256x256.md")
-GRID_SOURCES = ["k_grid_impl.hpp", "device_common.hpp", "sar_internal.hpp"]
+GRID_SOURCES = ["k_grid_impl.hpp", "k_grid_union.hpp", "device_common.hpp", "sar_internal.hpp"]
 
 
 def grid_kernel_hash():
