@@ -112,11 +112,14 @@ typedef enum { SAR_ECHO_C64 = 0, SAR_ECHO_F16X2 = 1 } sar_echo_type;
  *   tol 0 or in (0, 0.1]: target relative L2 error of the lateral NUFFT
  *   (0 selects 1e-3); the kernel width is the smallest whose calibrated
  *   error 5 exp(-pi W sqrt(1 - 1/sigma)) meets it;
- *   upsample 0 (automatic: 2, or what sar_plan_autotune stored for the plan's
- *   size bucket, see below) or in [1.25, 4] (SAR_ERR_UNSUPPORTED otherwise):
- *   the lateral grid has the smallest multiple of 8 cells of the form
- *   2^a 3^b 5^c at or above upsample * n along each axis, at most 4096
- *   (SAR_ERR_UNSUPPORTED beyond; sar_plan_info reports the effective ratio);
+ *   upsample 0 (automatic: what sar_plan_autotune stored for the plan's size
+ *   bucket, see below, else per axis a power of two between 1.5 n and 2 n if
+ *   there is one, else the grid of upsample 2) or in [1.25, 4]
+ *   (SAR_ERR_UNSUPPORTED otherwise): the lateral grid has the smallest
+ *   multiple of 8 cells of the form 2^a 3^b 5^c at or above upsample * n along
+ *   each axis (the next power of two instead when it is at most 1/8 larger),
+ *   at most 4096 cells (SAR_ERR_UNSUPPORTED beyond; sar_plan_info reports the
+ *   effective ratio);
  *   kernel_width 0 (from tol) or 3..8 taps;
  *   n_slabs 0 or 1 (one reference depth z_focus for the whole volume) or a
  *   power of two that divides nz: depth slabs, see below.
@@ -250,9 +253,10 @@ sar_status sar_backproject(sar_plan plan, const double* d_pos, int64_t n_pos, co
 /* Autotuner: times the whole pipeline on the given scan (which should be
  * representative of the plan's workload) for every candidate and keeps the
  * fastest for every later call of this plan.  Candidates: the lateral
- * oversampling (1.25, 1.5 and 2 when the plan was created with upsample = 0,
- * else only the requested one; the kernel width follows the plan's tolerance
- * at each) times every gridding tile configuration compiled for that width:
+ * oversampling (the automatic choice, 1.25, 1.5 and 2 when the plan was
+ * created with upsample = 0, else only the requested one; the kernel width
+ * follows the plan's tolerance at each) times every gridding tile
+ * configuration compiled for that width:
  *   0: 4 x 4 cells per wave, 2 frequencies per lane (kernels of 3 to 8 taps);
  *   1: 8 x 8 cells per wave, 1 frequency per lane (3 to 5 taps);
  *   2: 8 x 4 cells per wave, 2 frequencies per lane (5 and 6 taps);
@@ -261,7 +265,7 @@ sar_status sar_backproject(sar_plan plan, const double* d_pos, int64_t n_pos, co
  * sar_plan_workspace_bytes(plan, n_pos) are skipped, so d_workspace as sized
  * before the call stays large enough.  Runs each candidate a few times on
  * `stream` and waits for them (synchronous).  The default before tuning:
- * oversampling 2 (or the nearest 5-smooth grid, see upsample), tile 1 when the
+ * the automatic oversampling (see upsample), tile 1 when the
  * sweep has at most 64 frequencies (and the width allows it), else tile 3 for
  * kernels of up to 4 taps, else tile 0.  If the environment variable
  * SAR_AUTOTUNE_FILE names a file, the choice is also stored there for the

@@ -317,12 +317,13 @@ sar_status sar_plan_autotune(sar_plan plan, const double* d_pos, int64_t n_pos, 
   const size_t ws_have = workspace_bytes(p, n_pos, nullptr, nullptr);
   std::vector<Plan*> all{&p};
   for (auto& sub : p.slabs) all.push_back(sub.get());
-  const double cur_up = std::min((double)p.mx / p.nx, (double)p.my / p.ny);
+  // candidates: the requested oversampling, or the automatic choice (0) and
+  // three fixed ratios
   std::vector<double> sigmas;
   if (p.up_req > 0)
     sigmas.push_back(p.up_req);
   else
-    sigmas = {kMinUpsample, 1.5, 2.0};
+    sigmas = {0.0, kMinUpsample, 1.5, 2.0};
   auto adopt = [&](double up, int tile) -> sar_status {
     for (Plan* q : all) {
       sar_status s2 = choose_lateral(*q, up);
@@ -338,7 +339,7 @@ sar_status sar_plan_autotune(sar_plan plan, const double* d_pos, int64_t n_pos, 
     (void)hipEventDestroy(e0);
     return st;
   }
-  double best_up = cur_up;
+  double best_up = sigmas[0];
   int best_tile = p.grid_tile;
   float best_ms = 0.f;
   DirectSink sink(s);

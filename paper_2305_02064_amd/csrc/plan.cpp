@@ -37,6 +37,15 @@ int grid_length(int n, double sigma) {
   return (int)(8 * p2 <= 9 * m ? p2 : m);
 }
 
+// Automatic oversampling (upsample 0): a power of two between 1.5 n and 2 n
+// if there is one (the radix-2 transforms are the fastest, and oversampling
+// 1.5-2 needs at most one more kernel tap than 2), else the grid of
+// oversampling 2.
+int grid_length_auto(int n) {
+  const int64_t p2 = next_pow2((int64_t)std::ceil(1.5 * n - 1e-9));
+  return p2 <= 2 * (int64_t)n ? (int)p2 : grid_length(n, 2.0);
+}
+
 double bessel_i0_host(double x) {
   const double q = 0.25 * x * x;
   double term = 1.0, sum = 1.0;
@@ -133,8 +142,8 @@ double nufft_error_estimate(int W, double sigma) {
 // kernel width from the plan's tolerance (unless the descriptor fixed it), the
 // Kaiser-Bessel shape and the default gridding tile.
 sar_status choose_lateral(Plan& p, double up) {
-  const int mx = grid_length(p.nx, up);
-  const int my = grid_length(p.ny, up);
+  const int mx = up > 0 ? grid_length(p.nx, up) : grid_length_auto(p.nx);
+  const int my = up > 0 ? grid_length(p.ny, up) : grid_length_auto(p.ny);
   if (mx > kMaxFftLength || my > kMaxFftLength)
     return fail(SAR_ERR_UNSUPPORTED, "oversampled grid of " + std::to_string(mx) + " x " + std::to_string(my) +
                                          " cells: at most " + std::to_string(kMaxFftLength) + " per axis");
@@ -225,7 +234,8 @@ bool tuning_lookup(const Plan& p, double* sigma, int* tile) {
     if (eq == std::string::npos || line.compare(0, eq, key) != 0 || eq != key.size()) continue;
     double sg = 0;
     int t = -1;
-    if (std::sscanf(line.c_str() + eq + 3, "%lf %d", &sg, &t) == 2 && sg >= kMinUpsample && sg <= 4) {
+    if (std::sscanf(line.c_str() + eq + 3, "%lf %d", &sg, &t) == 2 &&
+        (sg == 0 || (sg >= kMinUpsample && sg <= 4))) {  // 0: the automatic choice
       *sigma = sg;
       *tile = t;
       found = true;  // the last entry for a key wins
@@ -334,10 +344,11 @@ sar_status build_plan(const sar_plan_desc* d, int device, Plan& p) {
   p.yc = p.y0 + (p.ny / 2) * p.dy;
 
   // lateral NUFFT: the requested oversampling, else the one tuned for this
-  // plan's size bucket (sar_plan_autotune with a tuning file), else 2
+  // plan's size bucket (sar_plan_autotune with a tuning file), else the
+  // automatic choice (up = 0, grid_length_auto)
   p.up_req = d->upsample;
   p.kw_req = d->kernel_width;
-  double up = d->upsample > 0 ? d->upsample : 2.0;
+  double up = d->upsample > 0 ? d->upsample : 0.0;
   int tuned_tile = -1;
   if (d->upsample == 0 && d->n_slabs <= 1) {
     double tuned_up = 0;

@@ -206,3 +206,4 @@ def test_wrappers_accept_matching_inputs_and_check_outputs(monkeypatch):
                             torch.zeros((3, 2, 5), dtype=torch.complex64), 1.0,
                             torch.zeros((8, 16, 5), dtype=torch.complex64), torch.zeros(16, dtype=torch.uint8))
     assert not calls
+

@@ -145,16 +145,39 @@ def test_mixed_radix_image_sides(torch_cuda, nx, ny):
                      dz=0.01, z_ref=0.0, z_focus=0.3)
     scan = _ragged_scan(500 + nx + ny, 149, 12, grid)
     ref = oracle.reconstruct_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, grid)
-    plan = make_plan(scan)
     pos, echo, _ = to_device(scan)
-    img = plan.reconstruct(pos, echo).cpu().numpy()
+    # oversampling 2 (mixed-radix grids for most sides), then the automatic
+    # choice (a power-of-two grid between 1.5 n and 2 n where there is one)
+    for up in (2.0, 0.0):
+        plan = make_plan(scan, upsample=up)
+        img = plan.reconstruct(pos, echo).cpu().numpy()
+        info = plan.info
+        plan.close()
+        err = rel_l2(img, ref)
+        print(f"sides {nx} x {ny}, upsample {up} (grid {info['mx']} x {info['my']}, width {info['width']}): "
+              f"image rel-L2 {err:.3e}")
+        assert info["mx"] % 8 == 0 and info["my"] % 8 == 0
+        if up == 2.0:
+            assert info["mx"] >= 2 * nx and info["my"] >= 2 * ny
+        else:
+            assert info["mx"] >= 1.5 * nx and info["my"] >= 1.5 * ny
+        assert err <= IMAGE_TOL
+        assert peak_ok(img, ref)
+
+
+@pytest.mark.parametrize("n,grid", [(32, 64), (96, 192), (150, 256), (162, 256), (100, 200), (512, 1024), (75, 128)])
+def test_automatic_oversampling_prefers_a_power_of_two(torch_cuda, n, grid):
+    # upsample 0: a power of two in [1.5 n, 2 n] if there is one, else the
+    # 5-smooth grid of oversampling 2; the kernel width follows the smaller
+    # oversampling (5 taps at 256 / 150, 4 at 2)
+    from paper_2305_02064_amd import sar
+    g = ImageGrid(nx=n, ny=n, nz=8, x0=-0.05, y0=-0.05, z0=0.25, dx=1e-3, dy=1e-3, dz=0.01, z_ref=0.0, z_focus=0.3)
+    plan = sar.Plan(*awr1443_layout(), sweep(16), g, 10)
     info = plan.info
     plan.close()
-    err = rel_l2(img, ref)
-    print(f"sides {nx} x {ny} (grid {info['mx']} x {info['my']}): image rel-L2 {err:.3e}")
-    assert info["mx"] % 8 == 0 and info["my"] % 8 == 0 and info["mx"] >= 2 * nx and info["my"] >= 2 * ny
-    assert err <= IMAGE_TOL
-    assert peak_ok(img, ref)
+    assert info["mx"] == grid and info["my"] == grid
+    sigma = grid / n
+    assert info["width"] == (4 if sigma >= 2 else 5)
 
 
 @pytest.mark.parametrize("upsample", [1.25, 1.5])
