@@ -260,14 +260,14 @@ sar_status sar_backproject(sar_plan plan, const double* d_pos, int64_t n_pos, co
  *   0: 4 x 4 cells per wave, 2 frequencies per lane (kernels of 3 to 8 taps);
  *   1: 8 x 8 cells per wave, 1 frequency per lane (3 to 5 taps);
  *   2: 8 x 4 cells per wave, 2 frequencies per lane (5 and 6 taps);
- *   3: 8 x 8 cells per 4-wave workgroup, 2 frequencies per lane (3 and 4 taps).
+ *   3: 8 x 8 cells per 4-wave workgroup, 2 frequencies per lane (3 to 5 taps).
  * Candidates whose workspace would exceed the plan's current
  * sar_plan_workspace_bytes(plan, n_pos) are skipped, so d_workspace as sized
  * before the call stays large enough.  Runs each candidate a few times on
  * `stream` and waits for them (synchronous).  The default before tuning:
  * the automatic oversampling (see upsample), tile 1 when the
  * sweep has at most 64 frequencies (and the width allows it), else tile 3 for
- * kernels of up to 4 taps, else tile 0.  If the environment variable
+ * kernels of up to 5 taps, else tile 0.  If the environment variable
  * SAR_AUTOTUNE_FILE names a file, the choice is also stored there for the
  * plan's size bucket (image and sweep sizes, pairs, echo type, flags,
  * tolerance, n_pos rounded up to a power of two), and plans created later

@@ -5,10 +5,11 @@
 // A workgroup owns a union of 8 x 8 grid cells for 128 frequencies (two
 // adjacent ones per lane, so a lane reads a sample's values with one 16-byte
 // LDS load and writes each cell with one 16-byte store).  Wave w owns the union's rows w and w + 4, all 8 columns: 2 x 8 x 2
-// complex accumulators per lane.  Every sample whose W x W support (W <= 4)
-// touches the union covers W consecutive rows, so it lands in at most one row
-// of each wave and every wave visits nearly every sample once: the waves stay
-// in step.  The union's samples (rows of first-tap cells, contiguous runs of
+// complex accumulators per lane.  Every sample whose W x W support touches
+// the union covers W consecutive rows, so for W <= 4 it lands in at most one
+// row of each wave (for W = 5 in both rows of a wave when its first tap row is
+// the wave's first row) and every wave visits nearly every sample once: the
+// waves stay in step.  The union's samples (rows of first-tap cells, contiguous runs of
 // the cell-sorted list) stream through LDS in chunks of 16: the four waves
 // stage a chunk's echo rows and kernel weights with gfx950's direct
 // global-to-LDS loads, then each compensates a quarter of the chunk in place
@@ -56,7 +57,7 @@ struct GridUnionBody {
 
 template <int W, int ET>
 __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uint32_t blk, uint32_t nblk) {
-  static_assert(W >= 2 && W <= 4, "one product row of four weights per wave and sample");
+  static_assert(W >= 2 && W <= 5, "tap rows of a sample meet at most two rows of a wave");
   constexpr int NWV = kUnionWaves;
   constexpr int UX = kUnionX;
   constexpr int UY = kUnionY;
@@ -70,13 +71,15 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
   constexpr int EB = FPL * 512;       // bytes of one sample's compensated values
   constexpr int NW = 2 * W;           // weight words per sample (wx then wy)
   constexpr int WS = (NW + 3) / 4 * 4;
+  constexpr int PR = W <= 4 ? 4 : 8;            // floats per product row (16 or 32 bytes)
+  constexpr int PSZ = W <= 4 ? 16 : W * PR;     // floats of products per sample
   constexpr int VOFF = 0;
   constexpr int WOFF = CH * EB;                 // raw weights (direct loads)
-  constexpr int POFF = WOFF + CH * WS * 4;      // products [CH][4 rows][4]
-  constexpr int BUF = POFF + CH * 64;
+  constexpr int POFF = WOFF + CH * WS * 4;      // products [CH][rows][PR]
+  constexpr int BUF = POFF + CH * PSZ * 4;
   static_assert(NA * NBX <= 256, "pattern chain covers 256 patterns");
-  static_assert(CH * WS <= 128, "weights of a chunk in two direct loads");
-  static_assert(CH * 16 == 64 * NWV, "one product per thread and chunk");
+  static_assert(CH * WS <= 64 * NWV, "weights of a chunk in one direct load per wave");
+  static_assert(CH * 16 == 64 * NWV, "one product row entry per thread and chunk (4-tap layout)");
   __shared__ int seg_s[NSEG];
   __shared__ int seg_off[NSEG + 1];
   __shared__ __attribute__((aligned(16))) char cbuf[2][BUF];
@@ -287,18 +290,20 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
       }
       *(float4*)(buf + VOFF + k * EB + lane * 16) = make_float4(u2[0].x, u2[0].y, u2[1].x, u2[1].y);
     }
-    // weight products: thread t forms product (jj, kk) of sample t / 16
-    {
-      const int t = threadIdx.x;
-      const int k = t >> 4;
-      const int jj = (t >> 2) & 3;
-      const int kk = t & 3;
+    // weight products: entry e = (sample, tap row jj, tap column kk) holds
+    // wx[kk] wy[jj] (one entry per thread for up to 4 taps)
+#pragma unroll
+    for (int e = threadIdx.x; e < CH * PSZ; e += 64 * NWV) {
+      const int k = e / PSZ;
+      const int r = e - k * PSZ;
+      const int jj = r / PR;
+      const int kk = r - jj * PR;
       float pr = 0.f;
       if (k < n && jj < W && kk < W) {
         const float* wk = (const float*)(buf + WOFF) + k * WS;
         pr = wk[kk] * wk[W + jj];
       }
-      ((float*)(buf + POFF))[t] = pr;
+      ((float*)(buf + POFF))[e] = pr;
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -319,30 +324,66 @@ __device__ __forceinline__ void GridUnionBody<W, ET>::run(const GridArgs& a, uin
       constexpr int AP = I / NBX - (NWV - 1);   // last-tap row offset from the wave's first row
       constexpr int BB = I % NBX;               // last-tap column offset
       constexpr int FR = AP - (W - 1);          // first-tap row offset
-      // the wave's row r (offset 4 r) takes tap row 4 r - FR if that is in [0, W)
+      // the wave's row r (offset 4 r) takes tap row 4 r - FR if that is in [0, W);
+      // a 5-tap sample whose first tap row is the wave's first row also meets
+      // the wave's second row (tap row 4)
       constexpr int R0 = (FR <= 0) ? 0 : (FR + NWV - 1) / NWV;
       constexpr int JJ = NWV * R0 - FR;
+      constexpr bool TWO = R0 + 1 < RPW && JJ + NWV < W;
       if constexpr (R0 < RPW && JJ >= 0 && JJ < W) {
-        typedef float f2v __attribute__((ext_vector_type(2)));
         typedef float f4v __attribute__((ext_vector_type(4)));
         f4v r;
-        f4v q;
+        float wp[W], wq[W];
         const uint32_t va = vbase + (uint32_t)(k * EB);
-        const uint32_t pa = pbase + (uint32_t)(k * 64);
-        asm volatile(
-            "ds_read_b128 %0, %2\n\t"
-            "ds_read_b128 %1, %3 offset:%4\n\ts_waitcnt lgkmcnt(0)"
-            : "=&v"(r), "=&v"(q)
-            : "v"(va), "v"(pa), "i"(JJ * 16)
-            : "memory");
-        const float wp[4] = {q.x, q.y, q.z, q.w};
+        const uint32_t pa = pbase + (uint32_t)(k * PSZ * 4);
+        if constexpr (W <= 4) {
+          f4v q;
+          asm volatile(
+              "ds_read_b128 %0, %2\n\t"
+              "ds_read_b128 %1, %3 offset:%4\n\ts_waitcnt lgkmcnt(0)"
+              : "=&v"(r), "=&v"(q)
+              : "v"(va), "v"(pa), "i"(JJ * 16)
+              : "memory");
+          const float q4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+          for (int i = 0; i < W; ++i) wp[i] = q4[i];
+        } else if constexpr (!TWO) {
+          f4v q;
+          float q5;
+          asm volatile(
+              "ds_read_b128 %0, %3\n\t"
+              "ds_read_b128 %1, %4 offset:%5\n\t"
+              "ds_read_b32 %2, %4 offset:%6\n\ts_waitcnt lgkmcnt(0)"
+              : "=&v"(r), "=&v"(q), "=&v"(q5)
+              : "v"(va), "v"(pa), "i"(JJ * PR * 4), "i"(JJ * PR * 4 + 16)
+              : "memory");
+          wp[0] = q.x; wp[1] = q.y; wp[2] = q.z; wp[3] = q.w; wp[4] = q5;
+        } else {
+          f4v q, s4;
+          float q5, s5;
+          asm volatile(
+              "ds_read_b128 %0, %5\n\t"
+              "ds_read_b128 %1, %6 offset:%7\n\t"
+              "ds_read_b32 %2, %6 offset:%8\n\t"
+              "ds_read_b128 %3, %6 offset:%9\n\t"
+              "ds_read_b32 %4, %6 offset:%10\n\ts_waitcnt lgkmcnt(0)"
+              : "=&v"(r), "=&v"(q), "=&v"(q5), "=&v"(s4), "=&v"(s5)
+              : "v"(va), "v"(pa), "i"(JJ * PR * 4), "i"(JJ * PR * 4 + 16), "i"((JJ + NWV) * PR * 4),
+                "i"((JJ + NWV) * PR * 4 + 16)
+              : "memory");
+          wp[0] = q.x; wp[1] = q.y; wp[2] = q.z; wp[3] = q.w; wp[4] = q5;
+          wq[0] = s4.x; wq[1] = s4.y; wq[2] = s4.z; wq[3] = s4.w; wq[4] = s5;
+        }
         const float2 v[FPL] = {make_float2(r.x, r.y), make_float2(r.z, r.w)};
         static_for<0, W>([&](auto kc) __attribute__((always_inline)) {
           constexpr int kk = decltype(kc)::value;
           constexpr int cc = BB - (W - 1) + kk;
           if constexpr (cc >= 0 && cc < UX) {
 #pragma unroll
-            for (int h = 0; h < FPL; ++h) cfma(acc[R0][cc][h], v[h], wp[kk]);
+            for (int h = 0; h < FPL; ++h) {
+              cfma(acc[R0][cc][h], v[h], wp[kk]);
+              if constexpr (TWO) cfma(acc[R0 + 1][cc][h], v[h], wq[kk]);
+            }
           }
         });
       }

@@ -167,7 +167,7 @@ sar_status choose_lateral(Plan& p, double up) {
   p.kb_beta = M_PI * std::sqrt(std::max(a * a - 0.8, 1e-6));
   // gridding tile: one frequency per lane when the sweep has at most 64
   // frequencies (two per lane would leave half the lanes idle), else the
-  // four-wave union (kernels of up to 4 taps) or the 4 x 4 tile; the
+  // four-wave union (kernels of up to 5 taps) or the 4 x 4 tile; the
   // autotuner may change it by timing
   if (p.nf <= 64 && grid_tile_compiled(1, p.w))
     p.grid_tile = 1;

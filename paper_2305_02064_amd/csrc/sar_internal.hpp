@@ -19,7 +19,7 @@ constexpr int kNumStages = 7;
 // compensated value, a wave per pair of rows four apart)
 constexpr int kNumGridTiles = 4;
 constexpr int kGridTiles[kNumGridTiles][3] = {{4, 4, 2}, {8, 8, 1}, {8, 4, 2}, {8, 8, 2}};
-constexpr int kGridTileWidths[kNumGridTiles][2] = {{3, 8}, {3, 5}, {5, 6}, {3, 4}};  // none spills registers
+constexpr int kGridTileWidths[kNumGridTiles][2] = {{3, 8}, {3, 5}, {5, 6}, {3, 5}};  // none spills registers
 constexpr bool grid_tile_compiled(int tile, int w) {
   return tile >= 0 && tile < kNumGridTiles && w >= kGridTileWidths[tile][0] && w <= kGridTileWidths[tile][1];
 }
