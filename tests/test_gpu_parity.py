@@ -441,6 +441,30 @@ def test_gridding_tiles_agree(torch_cuda, width, nf):
         assert rel_l2(spec, specs[0]) <= 1e-6
 
 
+@pytest.mark.parametrize("width,nf", [(3, 200), (5, 200), (5, 199)])
+def test_union_tile_half_precision_echo(torch_cuda, width, nf):
+    # FP16 echo storage (half pairs staged in the first half of a sample's LDS
+    # slot) through the four-wave union at 3 and 5 taps, and an odd sweep
+    # (single-value stores): equal to the one-wave tile up to summation order
+    from paper_2305_02064_amd import sar
+    grid = ImageGrid(nx=16, ny=32, nz=8, x0=-0.008, y0=-0.015, z0=0.25, dx=1e-3, dy=0.95e-3, dz=0.01,
+                     z_ref=0.0, z_focus=0.3)
+    scan = _ragged_scan(900 + width + nf, 211, nf, grid)
+    plan = make_plan(scan, kernel_width=width, echo_type=sar.SAR_ECHO_F16X2)
+    pos, echo, scale = to_device(scan, half=True)
+    out = []
+    for tile in (0, 3):
+        plan.set_grid_tile(tile)
+        out.append(plan.spectrum(pos, echo, echo_scale=scale).cpu().numpy())
+    plan.close()
+    ref = oracle.spectrum_direct(scan.pos, scan.tx_xy, scan.rx_xy, scan.freq, scan.echo, grid)
+    d, e = rel_l2(out[1], out[0]), rel_l2(out[1], ref)
+    print(f"FP16 echo, width {width}, nf {nf}: union vs one-wave tile {d:.2e}, vs oracle {e:.3e}")
+    assert d <= 1e-6
+    # the NUFFT estimate, or FP16 rounding of random values (~3e-4 rms)
+    assert e <= max(10 * np.exp(-np.pi * width * np.sqrt(0.5)), 1e-3)
+
+
 def test_autotune_keeps_a_working_tile(torch_cuda, tiny):
     from paper_2305_02064_amd import sar
     scan, _, img_ref = tiny
