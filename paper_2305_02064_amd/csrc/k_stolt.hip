@@ -94,6 +94,7 @@ __device__ __forceinline__ void StoltBody<MZ, WZ, F32>::run(const StoltArgs& a, 
   constexpr int L2 = MZ / kG;       // points per lane in the first FFT pass
   constexpr int WWIN = WZ + 2;      // register window of cells per lane
   constexpr int RB = 8;             // samples per lane whose loads are in flight together
+  constexpr int SB = 4;             // samples whose arithmetic is interleaved
   static_assert(MZ % kG == 0 && MZ <= 1024, "Stolt grid of 64..1024 cells");
   // LDS row of one column: MZ cells, then read back as the [16][L2 + 1]
   // padded transposition of the four-step FFT (one pad entry per row, so the
@@ -172,48 +173,64 @@ __device__ __forceinline__ void StoltBody<MZ, WZ, F32>::run(const StoltArgs& a, 
       };
       for (int r0 = 0; r0 < per; r0 += RB) {
         if (r0 > 0) load_batch(colc, r0);
+        // SB samples at a time: first their k_z, pre-phase, value, first
+        // cell and tap weights, with no branch, so the compiler interleaves
+        // the samples' long dependency chains; then their window updates
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          if (!((valid >> r) & 1u)) continue;
-          float kzs;   // filter factor: k_z, or 4k with the Jacobian
-          float2 ph;   // pre-phase exp(j k_z (z_mid - Z_0))
-          double gc;   // grid position (cells), not wrapped
-          if constexpr (F32) {
-            const float k = (float)kb[r];
-            const float kz2 = 4.f * k * k - kp2f;
-            if (!(kz2 > 0.f)) continue;
-            kzs = __builtin_sqrtf(kz2);
-            ph = cis_cycles_f32(kzs * (float)a.zmid_minus_zref_cyc);
-            gc = (double)(kzs * (float)a.dz_cells);
-            if (a.dcf) kzs = 4.f * k;
-          } else {
-            const double k = kb[r];
-            const double kz2 = 4.0 * k * k - kp2;
-            if (kz2 <= 0.0) continue;
-            const double kz = sqrt_pos(kz2);
-            kzs = a.dcf ? (float)(4.0 * k) : (float)kz;
-            ph = cis_cycles(kz * a.zmid_minus_zref_cyc);
-            gc = kz * a.dz_cells;
-          }
-          const float2 v = cscale(cmul(sb[r], ph), kzs * sgn);
-          const double a0 = gc - 0.5 * WZ;
-          const double c0d = floor(a0) + 1.0;
-          const int c0 = (int)c0d;
-          if (!open || c0 < wb || c0 + WZ > wb + WWIN) {
-            if (open) flush();
-            wb = c0;
-            open = true;
-          }
-          float wt[WZ];
-          es_taps<WZ>((float)(2.0 * (c0d - a0) - 1.0), wt);
-          // tap s lands in window cell o + s, o = c0 - wb in 0 .. WWIN - WZ
-          const int o = c0 - wb;
+        for (int r1 = 0; r1 < RB; r1 += SB) {
+          float2 vv[SB];
+          float ww[SB][WZ];
+          int cc[SB];
+          bool okk[SB];
 #pragma unroll
-          for (int s2 = 0; s2 < WWIN; ++s2) {
-            const float w0 = s2 < WZ ? wt[s2] : 0.f;
-            const float w1 = s2 >= 1 && s2 - 1 < WZ ? wt[s2 - 1] : 0.f;
-            const float w2 = s2 >= 2 && s2 - 2 < WZ ? wt[s2 - 2] : 0.f;
-            cfma(win[s2], v, o == 0 ? w0 : (o == 1 ? w1 : w2));
+          for (int q = 0; q < SB; ++q) {
+            const int r = r1 + q;
+            bool ok = (valid >> r) & 1u;
+            float kzs;   // filter factor: k_z, or 4k with the Jacobian
+            float2 ph;   // pre-phase exp(j k_z (z_mid - Z_0))
+            double gc;   // grid position (cells), not wrapped
+            if constexpr (F32) {
+              const float k = (float)kb[r];
+              const float kz2 = 4.f * k * k - kp2f;
+              ok = ok && kz2 > 0.f;
+              const float kzf = __builtin_sqrtf(ok ? kz2 : 1.f);   // evanescent: dropped below
+              ph = cis_cycles_f32(kzf * (float)a.zmid_minus_zref_cyc);
+              gc = (double)(kzf * (float)a.dz_cells);
+              kzs = a.dcf ? 4.f * k : kzf;
+            } else {
+              const double k = kb[r];
+              const double kz2 = 4.0 * k * k - kp2;
+              ok = ok && kz2 > 0.0;
+              const double kz = sqrt_pos(ok ? kz2 : 1.0);            // evanescent: dropped below
+              kzs = a.dcf ? (float)(4.0 * k) : (float)kz;
+              ph = cis_cycles(kz * a.zmid_minus_zref_cyc);
+              gc = kz * a.dz_cells;
+            }
+            vv[q] = cscale(cmul(sb[r], ph), kzs * sgn);
+            const double a0 = gc - 0.5 * WZ;
+            const double c0d = floor(a0) + 1.0;
+            cc[q] = (int)c0d;
+            es_taps<WZ>((float)(2.0 * (c0d - a0) - 1.0), ww[q]);
+            okk[q] = ok;
+          }
+#pragma unroll
+          for (int q = 0; q < SB; ++q) {
+            if (!okk[q]) continue;
+            const int c0 = cc[q];
+            if (!open || c0 < wb || c0 + WZ > wb + WWIN) {
+              if (open) flush();
+              wb = c0;
+              open = true;
+            }
+            // tap s lands in window cell o + s, o = c0 - wb in 0 .. WWIN - WZ
+            const int o = c0 - wb;
+#pragma unroll
+            for (int s2 = 0; s2 < WWIN; ++s2) {
+              const float w0 = s2 < WZ ? ww[q][s2] : 0.f;
+              const float w1 = s2 >= 1 && s2 - 1 < WZ ? ww[q][s2 - 1] : 0.f;
+              const float w2 = s2 >= 2 && s2 - 2 < WZ ? ww[q][s2 - 2] : 0.f;
+              cfma(win[s2], vv[q], o == 0 ? w0 : (o == 1 ? w1 : w2));
+            }
           }
         }
       }
