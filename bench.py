@@ -54,15 +54,22 @@ def recorded_traffic():
 
 
 def cpu_model():
-    """The host CPU's model name (first processor entry of /proc/cpuinfo)."""
+    """The host CPU's model name with its family, model, clock and cache
+    (first processor entry of /proc/cpuinfo; virtual machines often report a
+    bare vendor name, which the family and model numbers then identify)."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break  # end of the first processor entry
+                k, _, v = line.partition(":")
+                info.setdefault(k.strip(), v.strip())
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    name = info.get("model name", "unknown")
+    extra = [f"{k} {info[k]}" for k in ("cpu family", "model", "cpu MHz", "cache size") if k in info]
+    return f"{name} ({', '.join(extra)})" if extra else name
 
 
 def tiny_oracle_single_core():
