@@ -323,14 +323,19 @@ struct RadixScatterBody {
       kk[j] = valid ? a.key_in[i] : -1;
       vv[j] = valid ? (a.val_in ? a.val_in[i] : (int)i) : 0;
     }
-    for (int d = tid; d < NB; d += kSortThreads) base_d[d] = a.offs[(int64_t)d * a.ntiles + b];
+    for (int d = tid; d < NB; d += kSortThreads) {
+      base_d[d] = a.offs[(int64_t)d * a.ntiles + b];
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) wcnt[w][d] = 0;
+    }
+    __syncthreads();
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;   // lanes below this one
+    // per round, only the digits present are touched: the first lane of each
+    // digit group in a wave posts the group's count, and after the round adds
+    // it to the digit's next slot and clears its post (integer additions, so
+    // the slots do not depend on their order)
 #pragma unroll
     for (int j = 0; j < kSortRounds; ++j) {
-      for (int d = tid; d < NB; d += kSortThreads)
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) wcnt[w][d] = 0;
-      __syncthreads();
       const bool valid = kk[j] >= 0;
       const int d = (kk[j] >> a.shift) & (NB - 1);
       // lanes of this wave holding the same digit: they agree on every digit bit
@@ -342,7 +347,9 @@ struct RadixScatterBody {
         peers &= set ? m : ~m;
       }
       const int rank_w = __popcll(peers & lt);
-      if (valid && rank_w == 0) wcnt[wave][d] = __popcll(peers);
+      const bool lead = valid && rank_w == 0;
+      const int group = __popcll(peers);
+      if (lead) wcnt[wave][d] = group;
       __syncthreads();
       if (valid) {
         int pos = base_d[d] + rank_w;
@@ -351,11 +358,9 @@ struct RadixScatterBody {
         a.val_out[pos] = vv[j];
       }
       __syncthreads();
-      for (int dd = tid; dd < NB; dd += kSortThreads) {
-        int add = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) add += wcnt[w][dd];
-        base_d[dd] += add;
+      if (lead) {
+        atomicAdd(&base_d[d], group);
+        wcnt[wave][d] = 0;
       }
     }
   }
