@@ -250,6 +250,42 @@ struct ScanAddBody {
   }
 };
 
+// passes 2 + 3 in one for up to kScanFuseChunks chunks: each block sums the
+// raw totals of the chunks before its own (integer sums, so the offsets equal
+// those of the separate pass) and block 0 also writes the grand total
+constexpr int kScanFuseChunks = 1024;
+struct ScanAddSumsBody {
+  struct Args {
+    int32_t* data;
+    int64_t n;
+    const int32_t* bsum;   // raw chunk totals
+    int nb;
+    int32_t* total_out;
+  };
+  static constexpr int kThreads = kScanThreads;
+  static __device__ __forceinline__ void run(const Args& a, uint32_t b, uint32_t) {
+    __shared__ int smem[65];
+    const int upto = b == 0 ? a.nb : (int)b;   // block 0: every chunk, for the total
+    int v = threadIdx.x < upto ? a.bsum[threadIdx.x] : 0;
+    int total;
+    const int excl = block_exclusive_scan(v, smem, total);
+    // the sum of the chunks before b is the exclusive prefix at thread b
+    // (block 0: all of them, its own offset is 0)
+    __shared__ int off_s;
+    if (b != 0 && threadIdx.x == (int)b - 1) off_s = excl + v;
+    if (b == 0 && threadIdx.x == 0) {
+      off_s = 0;
+      *a.total_out = total;
+    }
+    __syncthreads();
+    const int off = off_s;
+    const int64_t base = (int64_t)b * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i)
+      if (base + i < a.n) a.data[base + i] += off;
+  }
+};
+
 // ---- stable least-significant-digit radix sort of the samples by cell -----
 // Each pass orders (key, index) pairs by one DB-bit digit of the key and keeps
 // the order of equal digits, so after the last pass the samples are sorted by
@@ -475,6 +511,7 @@ sar_status geometry_sort_w(const Plan& p, const double* d_pos, int64_t n_pos, in
     const int nb = (int)((n + kScanChunk - 1) / kScanChunk);
     sar_status s2;
     if ((s2 = launch_body<ScanLocalBody>(sink, nb, 0, {data, n, bsum}, what)) != SAR_OK) return s2;
+    if (nb <= kScanFuseChunks) return launch_body<ScanAddSumsBody>(sink, nb, 0, {data, n, bsum, nb, data + n}, what);
     if ((s2 = launch_body<ScanSumsBody>(sink, 1, 0, {bsum, nb, data + n}, what)) != SAR_OK) return s2;
     return launch_body<ScanAddBody>(sink, nb, 0, {data, n, bsum}, what);
   };
