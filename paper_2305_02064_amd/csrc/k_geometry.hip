@@ -134,7 +134,7 @@ struct KeysBody {
   }
 };
 
-// ---- exclusive scan of the per-cell counts (three passes) -----------------
+// ---- exclusive scans of counts (two passes, three beyond 1024 chunks) -----
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 4;
 constexpr int kScanChunk = kScanThreads * kScanItems;
