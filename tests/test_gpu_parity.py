@@ -136,6 +136,35 @@ def test_largest_transform_lengths(torch_cuda, nx, ny):
     assert err <= IMAGE_TOL
 
 
+def test_scan_of_more_than_1024_count_chunks(torch_cuda):
+    # a 2048 x 2048 image on a 4096 x 4096 grid: 16.8 M per-cell counts, more
+    # than 1024 chunks of 4096, so the cell-start scan takes its three-kernel
+    # form (smaller grids take the two-kernel one); spectrum at sampled
+    # entries against exact sums over every virtual sample
+    grid = ImageGrid(nx=2048, ny=2048, nz=2, x0=-1.024, y0=-1.024, z0=0.25, dx=1e-3, dy=1e-3, dz=0.01,
+                     z_ref=0.0, z_focus=0.3)
+    scan = _ragged_scan(2222, 301, 2, grid)
+    plan = make_plan(scan)
+    assert plan.info["mx"] * plan.info["my"] > 1024 * 4096
+    pos, echo, _ = to_device(scan)
+    spec = plan.spectrum(pos, echo).cpu().numpy()
+    plan.close()
+    rng = np.random.default_rng(5)
+    ne = 128
+    qi = rng.integers(0, grid.ny, ne)
+    pi = rng.integers(0, grid.nx, ne)
+    fi = rng.integers(0, 2, ne)
+    k = oracle.wavenumber(scan.freq)
+    xv, yv, dxx, dyy, dzz = oracle.virtual_samples(scan.pos, scan.tx_xy, scan.rx_xy, grid.z_ref)
+    beta = oracle.residual_path(dxx, dyy, dzz, grid.z_ref, grid.z_focus).ravel()
+    kx, ky, xc, yc = oracle.mode_axes(grid.nx, grid.ny, grid.x0, grid.y0, grid.dx, grid.dy)
+    shat = oracle.compensate(scan.echo.reshape(-1, 2), k, beta)
+    ref = oracle.nudft2_entries(shat, xv.ravel(), yv.ravel(), kx[pi], ky[qi], fi, xc, yc)
+    err = rel_l2(spec[qi, pi, fi], ref)
+    print(f"4096 x 4096 grid, {ne} sampled entries: rel-L2 {err:.3e}")
+    assert err <= IMAGE_TOL
+
+
 @pytest.mark.parametrize("nx,ny", [(72, 100), (75, 81), (150, 250), (250, 64), (135, 243), (125, 225)])
 def test_mixed_radix_image_sides(torch_cuda, nx, ny):
     # image sides of the form 2^a 3^b 5^c, odd ones included: oversampled grids
